@@ -1,0 +1,97 @@
+"""Pins of the float64 scheduler-network reference (``oracle.mlp_ref``).
+
+* gradients against central finite differences of the loss (a different
+  computation from back-propagation);
+* closed forms: zero weights give the output bias; with all pre-activations
+  positive the network is the affine map W3 W2 W1 x + (W3 W2 b1 + W3 b2 + b3);
+  an empty mask gives zero loss and gradient; the first Adam step moves each
+  parameter by lr * g / (|g| + eps) (bias-corrected moments equal g and g^2);
+* an invariant: Adam on a fixed batch drives the loss down.
+"""
+import numpy as np
+import pytest
+
+from oracle import mlp_ref as M
+
+F, H, P = 9, 32, 3
+
+
+def rand_theta(rng, scale=0.3):
+    return rng.normal(0, scale, size=M.n_params(F, H, P))
+
+
+def test_gradient_matches_finite_differences(rng):
+    X = rng.normal(0, 1, size=(40, F))
+    T = rng.normal(0, 1, size=(40, P))
+    Mk = (rng.random((40, P)) < 0.7).astype(np.float64)
+    th = rand_theta(rng)
+    L, g = M.loss_and_grad(th, X, T, Mk, F, H, P)
+    assert abs(L - M.loss(th, X, T, Mk, F, H, P)) < 1e-12
+    eps = 1e-6
+    idx = rng.choice(len(th), size=200, replace=False)
+    for i in idx:
+        tp = th.copy(); tp[i] += eps
+        tm = th.copy(); tm[i] -= eps
+        fd = (M.loss(tp, X, T, Mk, F, H, P) - M.loss(tm, X, T, Mk, F, H, P)) / (2 * eps)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(g[i])), (i, fd, g[i])
+
+
+def test_zero_weights_give_output_bias(rng):
+    th = np.zeros(M.n_params(F, H, P))
+    W1, b1, W2, b2, W3, b3 = M.unpack(th, F, H, P)
+    th[-P:] = [1.5, -2.0, 0.25]
+    y = M.forward(th, rng.normal(size=(5, F)), F, H, P)
+    np.testing.assert_array_equal(y, np.tile([1.5, -2.0, 0.25], (5, 1)))
+
+
+def test_positive_regime_is_affine(rng):
+    W1 = rng.random((H, F)); b1 = rng.random(H)
+    W2 = rng.random((H, H)); b2 = rng.random(H)
+    W3 = rng.normal(size=(P, H)); b3 = rng.normal(size=P)
+    th = M.pack(W1, b1, W2, b2, W3, b3)
+    X = rng.random((7, F))
+    A = W3 @ W2 @ W1
+    c = W3 @ W2 @ b1 + W3 @ b2 + b3
+    np.testing.assert_allclose(M.forward(th, X, F, H, P), X @ A.T + c, rtol=1e-12)
+
+
+def test_empty_mask(rng):
+    th = rand_theta(rng)
+    L, g = M.loss_and_grad(th, rng.normal(size=(4, F)), np.zeros((4, P)), np.zeros((4, P)), F, H, P)
+    assert L == 0.0 and not g.any()
+
+
+def test_first_adam_step_closed_form(rng):
+    th = rand_theta(rng)
+    g = rng.normal(size=th.shape)
+    lr, eps = 1e-3, 1e-8
+    th1, m1, v1 = M.adam_step(th, g, np.zeros_like(th), np.zeros_like(th), 1, lr, eps=eps)
+    np.testing.assert_allclose(th1, th - lr * g / (np.abs(g) + eps), rtol=1e-9, atol=1e-15)
+    np.testing.assert_allclose(m1, 0.1 * g)
+    np.testing.assert_allclose(v1, 0.001 * g * g)
+
+
+def test_adam_reduces_loss(rng):
+    X = rng.normal(size=(256, F))
+    true_w = rng.normal(size=(P, F))
+    T = X @ true_w.T
+    Mk = np.ones((256, P))
+    th = rand_theta(rng, 0.2)
+    m = np.zeros_like(th); v = np.zeros_like(th)
+    L0 = M.loss(th, X, T, Mk, F, H, P)
+    for t in range(1, 401):
+        _, g = M.loss_and_grad(th, X, T, Mk, F, H, P)
+        th, m, v = M.adam_step(th, g, m, v, t, 3e-3)
+    assert M.loss(th, X, T, Mk, F, H, P) < 0.1 * L0
+
+
+def test_f32_forward_close_to_f64(rng):
+    th = rand_theta(rng)
+    X = rng.normal(size=(64, F))
+    np.testing.assert_allclose(M.forward_f32(th, X, F, H, P), M.forward(th, X, F, H, P),
+                               rtol=1e-4, atol=1e-4)
+
+
+def test_bad_length_rejected():
+    with pytest.raises(ValueError):
+        M.unpack(np.zeros(10), F, H, P)
