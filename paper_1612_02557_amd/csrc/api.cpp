@@ -1,0 +1,744 @@
+// api.cpp -- the C interface: validation, planning, workspace, launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/raduls.h"
+#include "raduls_kernels.hpp"
+#include "raduls_plan.hpp"
+
+namespace {
+
+using rd::Plan;
+using rd::Work;
+
+constexpr uint32_t MLP_MODEL_FLOATS = RADULS_MLP_PARAMS + 2 * RADULS_MLP_F;
+constexpr uint32_t EPOCH_LIMIT = (1u << 22) - 64;  // look-back epochs before the status words are cleared
+
+thread_local std::string g_last_error;
+std::mutex g_mu;
+
+struct GraphKey {
+  void* records;
+  void* tmp;
+  const void* off;
+  uint32_t S;
+  uint64_t total;
+  uint32_t r, k;
+  std::string plan_bytes;
+  bool operator<(const GraphKey& o) const {
+    return std::tie(records, tmp, off, S, total, r, k, plan_bytes) <
+           std::tie(o.records, o.tmp, o.off, o.S, o.total, o.r, o.k, o.plan_bytes);
+  }
+};
+
+struct DeviceState {
+  int device = -1;
+  uint8_t* base = nullptr;       // lists, histograms, queues, stacks
+  size_t bytes = 0;
+  uint8_t* status_base = nullptr; // epoch counter + look-back words, kept apart so
+  size_t status_bytes = 0;        // that only status words ever live there
+  Work work{};
+  uint64_t epochs_used = 0;
+  uint64_t model_version = 0;
+  hipEvent_t last_done = nullptr;
+  hipStream_t last_stream = nullptr;
+  hipStream_t capture_stream = nullptr;
+  std::map<GraphKey, hipGraphExec_t> graphs;
+  float* model = nullptr;
+  raduls_trace_row* trace = nullptr;
+  uint64_t trace_cap = 0;
+  uint32_t sample_period = 0;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  bool timed = false;
+  int cu_count = 256;
+};
+
+std::map<int, DeviceState> g_dev;
+int g_sched_mode = RADULS_SCHED_HEURISTIC;
+int g_forced = 0;
+bool g_has_tuning = false;
+raduls_tuning g_tuning{};
+bool g_timing = false;
+bool g_model_loaded = false;
+std::vector<float> g_model_host;
+raduls_stats g_stats{};
+
+int fail(int code, const char* msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+  g_last_error = std::string(where) + ": " + hipGetErrorString(e);
+  return RADULS_EHIP;
+}
+
+#define HIPCHK(x)                                   \
+  do {                                              \
+    hipError_t e_ = (x);                            \
+    if (e_ != hipSuccess) return hip_fail(e_, #x);  \
+  } while (0)
+
+bool overlap(const void* a, const void* b, uint64_t bytes) {
+  uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+  return x < y + bytes && y < x + bytes;
+}
+
+int check_shape(uint32_t r, uint32_t k) {
+  if (k == 0 || r == 0) return fail(RADULS_EINVAL, "key_bytes and rec_bytes must be positive");
+  if (k > r) return fail(RADULS_EINVAL, "key_bytes exceeds rec_bytes");
+  if (k > 16) return fail(RADULS_EUNSUPPORTED, "key_bytes above 16");
+  if (r % 4 != 0) return fail(RADULS_EUNSUPPORTED, "rec_bytes must be a multiple of 4");
+  if (r > 64) return fail(RADULS_EUNSUPPORTED, "rec_bytes above 64");
+  return RADULS_OK;
+}
+
+uint32_t ipt_max(uint32_t rw) { return rw >= 2 ? 64 / rw : 32; }
+
+uint32_t pow2_floor(uint64_t x) {
+  uint32_t p = 1;
+  while ((uint64_t)p * 2 <= x) p *= 2;
+  return p;
+}
+
+raduls_tuning default_tuning(uint32_t r, uint32_t k, uint64_t n) {
+  (void)k;
+  (void)n;
+  raduls_tuning t{};
+  t.big_digit_bits = 8;
+  t.block_digit_bits = 8;
+  uint32_t tile = pow2_floor(std::min<uint64_t>(65536 / r, 256ull * ipt_max(r / 4)));
+  t.tile_records = std::min<uint32_t>(tile, 4096);
+  t.lds_finish_max = 0;
+  t.bitonic_max = 0;
+  t.workgroups_per_cu = 2;
+  t.big_min = 16ull * t.tile_records;
+  t.nontemporal = 0;
+  return t;
+}
+
+int validate_tuning(const raduls_tuning& t) {
+  if (t.big_digit_bits < 1 || t.big_digit_bits > 11) return fail(RADULS_EINVAL, "big_digit_bits must be 1..11");
+  if (t.block_digit_bits < 1 || t.block_digit_bits > 8) return fail(RADULS_EINVAL, "block_digit_bits must be 1..8");
+  if (t.tile_records < 256 || t.tile_records > 8192 || (t.tile_records & (t.tile_records - 1)))
+    return fail(RADULS_EINVAL, "tile_records must be a power of two in 256..8192");
+  if (t.bitonic_max && (t.bitonic_max & (t.bitonic_max - 1))) return fail(RADULS_EINVAL, "bitonic_max must be a power of two");
+  if (t.workgroups_per_cu < 1 || t.workgroups_per_cu > 8) return fail(RADULS_EINVAL, "workgroups_per_cu must be 1..8");
+  return RADULS_OK;
+}
+
+// Launch plan for n records (paper, Sec. 3.2: big bins above 2N/(3T)).
+Plan make_plan(uint64_t n, uint32_t r, uint32_t k, const raduls_tuning& t, int cus, uint32_t segs) {
+  Plan p{};
+  p.n = n;
+  p.rec_bytes = r;
+  p.key_bytes = k;
+  p.rw = r / 4;
+  p.d_big = t.big_digit_bits;
+  p.d_block = std::min<uint32_t>(t.block_digit_bits, 8);
+  uint32_t ipt = ipt_max(p.rw);
+  // tiles are whole rounds of 64 records per wavefront: powers of two >= 256
+  uint32_t tile = pow2_floor(std::min<uint32_t>(t.tile_records, 256 * ipt));
+  uint32_t stage_budget = p.d_big > 8 ? 32768 : 65536;
+  while (tile > 256 && (uint64_t)tile * r > stage_budget) tile /= 2;
+  p.tile = tile;
+  // single-workgroup kernel: LDS finishing capacity, bitonic capacity,
+  // wavefront capacity and radix-pass tile, within the dynamic LDS budget
+  const uint32_t dyn = 60 * 1024;
+  uint32_t cfin = 4096;
+  while (cfin > 256 && (uint64_t)cfin * r + std::max<uint64_t>(4ull * cfin, 16ull * std::min<uint32_t>(cfin, 1024)) > dyn)
+    cfin /= 2;
+  if (t.lds_finish_max) cfin = std::min<uint32_t>(cfin, std::max<uint32_t>(256, pow2_floor(t.lds_finish_max)));
+  p.c_fin = cfin;
+  uint32_t bmax = std::min<uint32_t>(cfin, 1024);
+  while ((uint64_t)cfin * r + 16ull * bmax > dyn && bmax > 64) bmax /= 2;
+  if (t.bitonic_max) bmax = std::min(bmax, t.bitonic_max);
+  p.bitonic_max = bmax;
+  uint32_t ws = 256;
+  while (ws > 64 && 4ull * (ws * r + 16ull * ws + 1024) > dyn) ws -= 64;
+  p.wave_cap = ws;
+  uint32_t bt = pow2_floor(256 * ipt);
+  while (bt > 256 && (uint64_t)bt * r > dyn) bt /= 2;
+  p.block_tile = std::min<uint32_t>(bt, 4096);
+  p.nontemporal = t.nontemporal;
+  p.grid_small = cus * t.workgroups_per_cu;
+  p.grid_scatter = cus * 2;
+  p.grid_hist = cus * 4;
+  p.grid_clear = cus * 4;
+  uint64_t W = p.grid_small;
+  p.t_big = std::max<uint64_t>(2 * n / (3 * W), std::max<uint64_t>(t.big_min, (uint64_t)p.c_fin));
+  uint32_t kb = 8 * k;
+  p.lmax = std::min<uint32_t>((kb + p.d_big - 1) / p.d_big + 1, rd::LMAX);
+  p.cap_big = n / (p.t_big + 1) + 2;
+  uint64_t R = 1ull << p.d_big;
+  uint64_t child_bound = R * p.lmax * p.cap_big + segs + 1;
+  p.cap_small = std::min<uint64_t>(n / 33 + 1, child_bound) + 1;
+  p.cap_tiny = std::min<uint64_t>(n + 1, child_bound) + 1;
+  p.cap_copy = std::min<uint64_t>(n / 64 + 1, child_bound) + 1;
+  p.max_tiles = n / p.tile + p.cap_big + 2;
+  p.stack_cap = (uint32_t)std::min<uint64_t>(p.t_big / (p.c_fin + 1) + 4, 1u << 20);
+  p.sched_mode = g_sched_mode;
+  p.forced_proc = g_forced;
+  p.segmented = segs ? 1 : 0;
+  return p;
+}
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+  size_t ctl, big, tile_start, hist, vary, small, small_ord, tiny, copy, copy_start, stacks, trace_count, total;
+  size_t status_total;  // epoch counter (256 bytes) + look-back words
+};
+
+Layout layout_of(const Plan& p) {
+  Layout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
+  uint64_t R = 1ull << p.d_big;
+  L.ctl = take(sizeof(rd::Ctl));
+  L.big = take((size_t)(p.lmax + 1) * p.cap_big * sizeof(rd::Bucket));
+  L.tile_start = take((size_t)(p.lmax + 1) * (p.cap_big + 1) * 8);
+  L.hist = take((size_t)p.cap_big * R * 8);
+  L.vary = take((size_t)p.cap_big * 16);
+  L.small = take((size_t)p.cap_small * sizeof(rd::Bucket));
+  L.small_ord = take((size_t)p.cap_small * sizeof(rd::Bucket));
+  L.tiny = take((size_t)p.cap_tiny * 8);
+  L.copy = take((size_t)p.cap_copy * sizeof(rd::Bucket));
+  L.copy_start = take((size_t)(p.cap_copy + 1) * 8);
+  L.stacks = take((size_t)p.grid_small * p.stack_cap * sizeof(rd::Bucket));
+  L.trace_count = take(8);
+  L.total = o;
+  L.status_total = 256 + align_up((size_t)p.max_tiles * R * 8);
+  return L;
+}
+
+DeviceState& state_for(int dev) {
+  DeviceState& s = g_dev[dev];
+  if (s.device < 0) {
+    s.device = dev;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+      s.cu_count = cus;
+  }
+  return s;
+}
+
+void drop_graphs(DeviceState& s) {
+  for (auto& kv : s.graphs) hipGraphExecDestroy(kv.second);
+  s.graphs.clear();
+}
+
+// Make sure the workspace holds the plan's layout.  The look-back words live
+// in an allocation of their own, zeroed when it is (re)allocated and when the
+// epochs run out, so a stale word can only be an old status word.
+int ensure_workspace(DeviceState& s, const Plan& p, Layout& L, hipStream_t stream) {
+  L = layout_of(p);
+  if (getenv("RADULS_TEST_FAIL_ALLOC") && (L.total > s.bytes || L.status_total > s.status_bytes))
+    return fail(RADULS_ENOMEM, "workspace allocation refused (test hook)");
+  if (L.total > s.bytes) {
+    if (s.base) {
+      HIPCHK(hipDeviceSynchronize());
+      drop_graphs(s);
+      hipFree(s.base);
+      s.base = nullptr;
+      s.bytes = 0;
+    }
+    size_t want = L.total + L.total / 8;
+    if (hipMalloc(&s.base, want) != hipSuccess) {
+      (void)hipGetLastError();
+      s.base = nullptr;
+      return fail(RADULS_ENOMEM, "workspace allocation failed");
+    }
+    s.bytes = want;
+    HIPCHK(hipMemsetAsync(s.base, 0, want, stream));
+    drop_graphs(s);
+  }
+  if (L.status_total > s.status_bytes) {
+    if (s.status_base) {
+      HIPCHK(hipDeviceSynchronize());
+      drop_graphs(s);
+      hipFree(s.status_base);
+      s.status_base = nullptr;
+      s.status_bytes = 0;
+    }
+    size_t want = L.status_total + L.status_total / 8;
+    if (hipMalloc(&s.status_base, want) != hipSuccess) {
+      (void)hipGetLastError();
+      s.status_base = nullptr;
+      return fail(RADULS_ENOMEM, "look-back allocation failed");
+    }
+    s.status_bytes = want;
+    HIPCHK(hipMemsetAsync(s.status_base, 0, want, stream));
+    s.epochs_used = 0;
+  } else if (s.epochs_used + rd::LMAX + 1 >= EPOCH_LIMIT) {
+    HIPCHK(hipMemsetAsync(s.status_base, 0, s.status_bytes, stream));
+    s.epochs_used = 0;
+  }
+  Work& w = s.work;
+  w.ctl = (rd::Ctl*)(s.base + L.ctl);
+  w.big = (rd::Bucket*)(s.base + L.big);
+  w.tile_start = (uint64_t*)(s.base + L.tile_start);
+  w.hist = (uint64_t*)(s.base + L.hist);
+  w.vary = (uint64_t*)(s.base + L.vary);
+  w.status = (uint64_t*)(s.status_base + 256);
+  w.small = (rd::Bucket*)(s.base + L.small);
+  w.small_ord = (rd::Bucket*)(s.base + L.small_ord);
+  w.tiny = (uint64_t*)(s.base + L.tiny);
+  w.copy = (rd::Bucket*)(s.base + L.copy);
+  w.copy_start = (uint64_t*)(s.base + L.copy_start);
+  w.stacks = (rd::Bucket*)(s.base + L.stacks);
+  w.model = g_model_loaded ? s.model : nullptr;
+  w.trace = s.trace;
+  w.trace_count = (uint64_t*)(s.base + L.trace_count);
+  w.counts_out = nullptr;
+  w.epoch_counter = (uint32_t*)s.status_base;
+  return RADULS_OK;
+}
+
+uint64_t g_model_version = 0;
+
+int ensure_model(DeviceState& s) {
+  if (!g_model_loaded || s.model_version == g_model_version) return RADULS_OK;
+  if (!s.model) HIPCHK(hipMalloc(&s.model, MLP_MODEL_FLOATS * sizeof(float)));
+  HIPCHK(hipMemcpy(s.model, g_model_host.data(), MLP_MODEL_FLOATS * sizeof(float), hipMemcpyHostToDevice));
+  s.model_version = g_model_version;
+  return RADULS_OK;
+}
+
+// Order this call after the previous one that used the workspace.
+int order_after_previous(DeviceState& s, hipStream_t stream) {
+  if (s.last_done && s.last_stream != stream) HIPCHK(hipStreamWaitEvent(stream, s.last_done, 0));
+  return RADULS_OK;
+}
+
+int mark_done(DeviceState& s, hipStream_t stream) {
+  if (!s.last_done) HIPCHK(hipEventCreateWithFlags(&s.last_done, hipEventDisableTiming));
+  HIPCHK(hipEventRecord(s.last_done, stream));
+  s.last_stream = stream;
+  return RADULS_OK;
+}
+
+raduls_tuning current_tuning(uint32_t r, uint32_t k, uint64_t n) {
+  return g_has_tuning ? g_tuning : default_tuning(r, k, n);
+}
+
+// The launch sequence of one sort.  Every kernel reads its work from
+// device-side lists, so the sequence is the same for any data and can be
+// captured into a graph.
+void enqueue_sort(DeviceState& s, const Plan& p, void* records, void* tmp, const uint64_t* off, uint32_t S,
+                  hipStream_t st) {
+  rd::launch_init(s.work, st);
+  if (off) rd::launch_seed_segments(p, s.work, off, S, st);
+  else rd::launch_seed_single(p, s.work, st);
+  for (uint32_t l = 0; l < p.lmax; l++) rd::launch_level(p, s.work, l, records, tmp, st);
+  rd::launch_order_small(p, s.work, st);
+  rd::launch_small(p, s.work, records, tmp, st);
+  rd::launch_copy(p, s.work, records, tmp, st);
+}
+
+int prepare(DeviceState& s, Plan& p, Layout& L, hipStream_t st) {
+  int rc = ensure_workspace(s, p, L, st);
+  if (rc) return rc;
+  rc = ensure_model(s);
+  if (rc) return rc;
+  p.has_model = g_model_loaded ? 1 : 0;
+  p.trace_cap = s.trace ? s.trace_cap : 0;
+  p.sample_period = s.trace ? s.sample_period : 0;
+  s.work.model = g_model_loaded ? s.model : nullptr;
+  s.work.trace = s.trace;
+  return RADULS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int raduls_sort(void* records, void* tmp, uint64_t n, uint32_t rec_bytes, uint32_t key_bytes, void* stream) {
+  int rc = check_shape(rec_bytes, key_bytes);
+  if (rc) return rc;
+  if (n <= 1) return RADULS_OK;
+  if (!records || !tmp) return fail(RADULS_EINVAL, "null records or tmp");
+  if (n >= (1ull << 40)) return fail(RADULS_EUNSUPPORTED, "n must be below 2^40");
+  if (((uintptr_t)records & 15) || ((uintptr_t)tmp & 15)) return fail(RADULS_EINVAL, "buffers must be 16-byte aligned");
+  if (overlap(records, tmp, n * rec_bytes)) return fail(RADULS_EINVAL, "records and tmp overlap");
+  std::lock_guard<std::mutex> lock(g_mu);
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  DeviceState& s = state_for(dev);
+  hipStream_t st = (hipStream_t)stream;
+  raduls_tuning t = current_tuning(rec_bytes, key_bytes, n);
+  Plan p = make_plan(n, rec_bytes, key_bytes, t, s.cu_count, 0);
+  Layout L;
+  rc = prepare(s, p, L, st);
+  if (rc) return rc;
+  rc = order_after_previous(s, st);
+  if (rc) return rc;
+  if (g_timing) {
+    if (!s.t0) { HIPCHK(hipEventCreate(&s.t0)); HIPCHK(hipEventCreate(&s.t1)); }
+    HIPCHK(hipEventRecord(s.t0, st));
+  }
+  enqueue_sort(s, p, records, tmp, nullptr, 0, st);
+  HIPCHK(hipGetLastError());
+  if (g_timing) { HIPCHK(hipEventRecord(s.t1, st)); s.timed = true; }
+  s.epochs_used += rd::LMAX + 1;
+  g_stats.last_records = n;
+  g_stats.last_levels = p.lmax;
+  return mark_done(s, st);
+}
+
+int raduls_sort_segmented(void* records, void* tmp, const uint64_t* seg_offsets, uint32_t num_segs,
+                          uint64_t total_records, uint32_t rec_bytes, uint32_t key_bytes, void* stream) {
+  int rc = check_shape(rec_bytes, key_bytes);
+  if (rc) return rc;
+  if (num_segs == 0 || total_records == 0) return RADULS_OK;
+  if (!records || !tmp || !seg_offsets) return fail(RADULS_EINVAL, "null pointer");
+  if (total_records >= (1ull << 40)) return fail(RADULS_EUNSUPPORTED, "total_records must be below 2^40");
+  if (((uintptr_t)records & 15) || ((uintptr_t)tmp & 15)) return fail(RADULS_EINVAL, "buffers must be 16-byte aligned");
+  if (((uintptr_t)seg_offsets & 7)) return fail(RADULS_EINVAL, "seg_offsets must be 8-byte aligned");
+  if (overlap(records, tmp, total_records * rec_bytes)) return fail(RADULS_EINVAL, "records and tmp overlap");
+  std::lock_guard<std::mutex> lock(g_mu);
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  DeviceState& s = state_for(dev);
+  hipStream_t st = (hipStream_t)stream;
+  raduls_tuning t = current_tuning(rec_bytes, key_bytes, total_records);
+  Plan p = make_plan(total_records, rec_bytes, key_bytes, t, s.cu_count, num_segs);
+  Layout L;
+  rc = prepare(s, p, L, st);
+  if (rc) return rc;
+  rc = order_after_previous(s, st);
+  if (rc) return rc;
+  if (!s.capture_stream) HIPCHK(hipStreamCreateWithFlags(&s.capture_stream, hipStreamNonBlocking));
+  GraphKey key{records, tmp, seg_offsets, num_segs, total_records, rec_bytes, key_bytes,
+               std::string((const char*)&p, sizeof(Plan))};
+  auto it = s.graphs.find(key);
+  hipGraphExec_t exec = nullptr;
+  if (it != s.graphs.end()) {
+    exec = it->second;
+  } else {
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(s.capture_stream, hipStreamCaptureModeThreadLocal));
+    enqueue_sort(s, p, records, tmp, seg_offsets, num_segs, s.capture_stream);
+    hipError_t e = hipStreamEndCapture(s.capture_stream, &g);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    s.graphs[key] = exec;
+  }
+  if (g_timing) {
+    if (!s.t0) { HIPCHK(hipEventCreate(&s.t0)); HIPCHK(hipEventCreate(&s.t1)); }
+    HIPCHK(hipEventRecord(s.t0, st));
+  }
+  HIPCHK(hipGraphLaunch(exec, st));
+  if (g_timing) { HIPCHK(hipEventRecord(s.t1, st)); s.timed = true; }
+  s.epochs_used += rd::LMAX + 1;
+  g_stats.last_records = total_records;
+  g_stats.last_levels = p.lmax;
+  return mark_done(s, st);
+}
+
+int raduls_partition(const void* in, void* out, uint64_t n, uint32_t rec_bytes, uint32_t key_bytes, uint32_t shift,
+                     uint32_t bits, uint64_t* counts, void* stream) {
+  int rc = check_shape(rec_bytes, key_bytes);
+  if (rc) return rc;
+  if (bits < 1 || bits > 11) return fail(RADULS_EINVAL, "bits must be 1..11");
+  if (shift + bits > 8 * key_bytes) return fail(RADULS_EINVAL, "digit must lie inside the key");
+  if (n == 0) return RADULS_OK;
+  if (!in || !out) return fail(RADULS_EINVAL, "null pointer");
+  if (n >= (1ull << 40)) return fail(RADULS_EUNSUPPORTED, "n must be below 2^40");
+  if (((uintptr_t)in & 15) || ((uintptr_t)out & 15)) return fail(RADULS_EINVAL, "buffers must be 16-byte aligned");
+  if (overlap(in, out, n * rec_bytes)) return fail(RADULS_EINVAL, "in and out overlap");
+  std::lock_guard<std::mutex> lock(g_mu);
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  DeviceState& s = state_for(dev);
+  hipStream_t st = (hipStream_t)stream;
+  raduls_tuning t = current_tuning(rec_bytes, key_bytes, n);
+  t.big_digit_bits = bits;
+  Plan p = make_plan(n, rec_bytes, key_bytes, t, s.cu_count, 0);
+  p.lmax = 1;
+  p.partition = 1;
+  p.t_big = 0;
+  p.cap_big = 2;
+  p.max_tiles = n / p.tile + 4;
+  Layout L;
+  rc = prepare(s, p, L, st);
+  if (rc) return rc;
+  rc = order_after_previous(s, st);
+  if (rc) return rc;
+  s.work.counts_out = counts;
+  p.partition_bit = 8 * key_bytes - shift - bits;
+  rd::launch_init(s.work, st);
+  rd::launch_seed_single(p, s.work, st);
+  rd::launch_level(p, s.work, 0, const_cast<void*>(in), out, st);
+  HIPCHK(hipGetLastError());
+  s.work.counts_out = nullptr;
+  s.epochs_used += rd::LMAX + 1;
+  return mark_done(s, st);
+}
+
+int raduls_sync_check(void* stream) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+  auto it = g_dev.find(dev);
+  if (it == g_dev.end() || !it->second.base) return RADULS_OK;
+  rd::Ctl c;
+  HIPCHK(hipMemcpy(&c, it->second.work.ctl, sizeof(c), hipMemcpyDeviceToHost));
+  if (c.error & 1u) return fail(RADULS_EDEVICE, "segment offsets invalid (must start at 0, not decrease, end at total)");
+  if (c.error & 2u) return fail(RADULS_EDEVICE, "look-back wait limit reached");
+  if (c.overflow) return fail(RADULS_EDEVICE, "a device queue overflowed");
+  return RADULS_OK;
+}
+
+int raduls_set_scheduler(int mode, int forced_proc) {
+  if (mode < RADULS_SCHED_HEURISTIC || mode > RADULS_SCHED_FORCED) return fail(RADULS_EINVAL, "unknown scheduler mode");
+  if (mode == RADULS_SCHED_FORCED && (forced_proc < 0 || forced_proc > RADULS_PROC_BITONIC))
+    return fail(RADULS_EINVAL, "forced_proc must be RADIX, LSD or BITONIC");
+  std::lock_guard<std::mutex> lock(g_mu);
+  g_sched_mode = mode;
+  g_forced = forced_proc;
+  g_stats.sched_mode = mode;
+  return RADULS_OK;
+}
+
+int raduls_get_scheduler(int* mode, int* forced_proc) {
+  if (!mode || !forced_proc) return fail(RADULS_EINVAL, "null pointer");
+  *mode = g_sched_mode;
+  *forced_proc = g_forced;
+  return RADULS_OK;
+}
+
+static uint32_t fnv1a(const uint8_t* p, size_t n) {
+  uint32_t h = 2166136261u;
+  for (size_t i = 0; i < n; i++) { h ^= p[i]; h *= 16777619u; }
+  return h;
+}
+
+int raduls_load_model(const void* host_blob, size_t bytes) {
+  const size_t want = 8 + 12 + (size_t)MLP_MODEL_FLOATS * 4 + 4;
+  if (!host_blob || bytes != want) return fail(RADULS_EMODEL, "model blob has the wrong size");
+  const uint8_t* b = (const uint8_t*)host_blob;
+  if (memcmp(b, "RDLSMLP1", 8) != 0) return fail(RADULS_EMODEL, "model blob header mismatch");
+  uint32_t dims[3];
+  memcpy(dims, b + 8, 12);
+  if (dims[0] != RADULS_MLP_F || dims[1] != RADULS_MLP_H || dims[2] != RADULS_MLP_P)
+    return fail(RADULS_EMODEL, "model dimensions differ from 9/32/3");
+  uint32_t sum;
+  memcpy(&sum, b + want - 4, 4);
+  if (fnv1a(b, want - 4) != sum) return fail(RADULS_EMODEL, "model checksum mismatch");
+  std::vector<float> v(MLP_MODEL_FLOATS);
+  memcpy(v.data(), b + 20, (size_t)MLP_MODEL_FLOATS * 4);
+  for (uint32_t i = 0; i < MLP_MODEL_FLOATS; i++)
+    if (!std::isfinite(v[i])) return fail(RADULS_EMODEL, "model holds a non-finite value");
+  for (uint32_t i = 0; i < RADULS_MLP_F; i++)
+    if (!(v[RADULS_MLP_PARAMS + RADULS_MLP_F + i] > 0.0f)) return fail(RADULS_EMODEL, "feature scale must be positive");
+  std::lock_guard<std::mutex> lock(g_mu);
+  g_model_host = v;
+  g_model_loaded = true;
+  g_model_version++;
+  g_stats.model_params = RADULS_MLP_PARAMS;
+  return RADULS_OK;
+}
+
+int raduls_unload_model(void) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  g_model_loaded = false;
+  g_stats.model_params = 0;
+  return RADULS_OK;
+}
+
+int raduls_set_tuning(const raduls_tuning* t) {
+  if (!t) {
+    std::lock_guard<std::mutex> lock(g_mu);
+    g_has_tuning = false;
+    return RADULS_OK;
+  }
+  int rc = validate_tuning(*t);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lock(g_mu);
+  g_tuning = *t;
+  g_has_tuning = true;
+  return RADULS_OK;
+}
+
+int raduls_get_tuning(raduls_tuning* t) {
+  if (!t) return fail(RADULS_EINVAL, "null pointer");
+  if (!g_has_tuning) return fail(RADULS_EINVAL, "no tuning set (defaults in use)");
+  *t = g_tuning;
+  return RADULS_OK;
+}
+
+int raduls_default_tuning(uint32_t rec_bytes, uint32_t key_bytes, uint64_t n, raduls_tuning* t) {
+  if (!t) return fail(RADULS_EINVAL, "null pointer");
+  int rc = check_shape(rec_bytes, key_bytes);
+  if (rc) return rc;
+  *t = default_tuning(rec_bytes, key_bytes, n);
+  return RADULS_OK;
+}
+
+int raduls_set_trace(void* rows, uint64_t capacity, uint32_t sample_period) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  DeviceState& s = state_for(dev);
+  s.trace = rows ? (raduls_trace_row*)rows : nullptr;
+  s.trace_cap = rows ? capacity : 0;
+  s.sample_period = rows ? sample_period : 0;
+  if (s.base) {
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(hipMemset(s.work.trace_count, 0, 8));
+  }
+  drop_graphs(s);
+  return RADULS_OK;
+}
+
+int raduls_trace_count(uint64_t* host_count, void* stream) {
+  if (!host_count) return fail(RADULS_EINVAL, "null pointer");
+  std::lock_guard<std::mutex> lock(g_mu);
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+  auto it = g_dev.find(dev);
+  *host_count = 0;
+  if (it == g_dev.end() || !it->second.base) return RADULS_OK;
+  HIPCHK(hipMemcpy(host_count, it->second.work.trace_count, 8, hipMemcpyDeviceToHost));
+  return RADULS_OK;
+}
+
+int raduls_set_timing(int on) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  g_timing = on != 0;
+  return RADULS_OK;
+}
+
+int raduls_get_stats(raduls_stats* out) {
+  if (!out) return fail(RADULS_EINVAL, "null pointer");
+  std::lock_guard<std::mutex> lock(g_mu);
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  raduls_stats st = g_stats;
+  st.last_ms = 0;
+  auto it = g_dev.find(dev);
+  if (it != g_dev.end()) {
+    DeviceState& s = it->second;
+    if (s.timed && s.t1) {
+      HIPCHK(hipEventSynchronize(s.t1));
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, s.t0, s.t1));
+      st.last_ms = ms;
+    }
+    st.workspace_bytes = s.bytes;
+    st.graph_cache_entries = s.graphs.size();
+  }
+  st.sched_mode = g_sched_mode;
+  *out = st;
+  return RADULS_OK;
+}
+
+size_t raduls_workspace_bytes(uint64_t n, uint32_t rec_bytes, uint32_t key_bytes) {
+  if (check_shape(rec_bytes, key_bytes) != RADULS_OK) return 0;
+  raduls_tuning t = current_tuning(rec_bytes, key_bytes, n);
+  int cus = 256;
+  int dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int c = 0;
+    if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && c > 0) cus = c;
+  } else {
+    (void)hipGetLastError();
+  }
+  Plan p = make_plan(n, rec_bytes, key_bytes, t, cus, 0);
+  Layout L = layout_of(p);
+  return L.total + L.status_total;
+}
+
+const char* raduls_status_string(int status) {
+  switch (status) {
+    case RADULS_OK: return "ok";
+    case RADULS_EINVAL: return "invalid argument";
+    case RADULS_ENOMEM: return "out of device memory";
+    case RADULS_EHIP: return "HIP runtime error";
+    case RADULS_EUNSUPPORTED: return "unsupported shape";
+    case RADULS_EMODEL: return "model rejected";
+    case RADULS_EDEVICE: return "device-side check failed";
+    default: return "unknown status";
+  }
+}
+
+const char* raduls_last_error_message(void) { return g_last_error.c_str(); }
+
+void raduls_release(void) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  for (auto& kv : g_dev) {
+    DeviceState& s = kv.second;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(s.device);
+    (void)hipDeviceSynchronize();
+    drop_graphs(s);
+    if (s.base) hipFree(s.base);
+    if (s.status_base) hipFree(s.status_base);
+    if (s.model) hipFree(s.model);
+    if (s.last_done) hipEventDestroy(s.last_done);
+    if (s.t0) hipEventDestroy(s.t0);
+    if (s.t1) hipEventDestroy(s.t1);
+    if (s.capture_stream) hipStreamDestroy(s.capture_stream);
+    (void)hipSetDevice(cur);
+  }
+  g_dev.clear();
+}
+
+// ---- scheduler-network kernels ----------------------------------------------
+
+int raduls_mlp_forward(const float* X, const float* theta, float* Y, uint32_t batch, void* stream) {
+  if (!X || !theta || !Y) return fail(RADULS_EINVAL, "null pointer");
+  if (batch == 0) return RADULS_OK;
+  rd::launch_mlp_forward(X, theta, Y, batch, (hipStream_t)stream);
+  HIPCHK(hipGetLastError());
+  return RADULS_OK;
+}
+
+int raduls_mlp_loss_grad(const float* X, const float* T, const float* M, const float* theta, float* grad, float* loss,
+                         uint32_t batch, void* stream) {
+  if (!X || !T || !M || !theta || !grad || !loss) return fail(RADULS_EINVAL, "null pointer");
+  std::lock_guard<std::mutex> lock(g_mu);
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  DeviceState& s = state_for(dev);
+  static thread_local std::map<int, std::pair<float*, size_t>> scratch;
+  size_t need = rd::mlp_scratch_floats(batch) * sizeof(float);
+  auto& sc = scratch[dev];
+  if (sc.second < need) {
+    if (sc.first) { HIPCHK(hipDeviceSynchronize()); hipFree(sc.first); }
+    sc.first = nullptr;
+    sc.second = 0;
+    if (hipMalloc(&sc.first, need) != hipSuccess) { (void)hipGetLastError(); return fail(RADULS_ENOMEM, "scratch"); }
+    sc.second = need;
+  }
+  (void)s;
+  rd::launch_mlp_loss_grad(X, T, M, theta, grad, loss, sc.first, batch, (hipStream_t)stream);
+  HIPCHK(hipGetLastError());
+  return RADULS_OK;
+}
+
+int raduls_mlp_adam(float* theta, const float* grad, float* m, float* v, uint32_t t, float lr, float beta1, float beta2,
+                    float eps, void* stream) {
+  if (!theta || !grad || !m || !v) return fail(RADULS_EINVAL, "null pointer");
+  if (t == 0) return fail(RADULS_EINVAL, "Adam steps count from 1");
+  rd::launch_mlp_adam(theta, grad, m, v, t, lr, beta1, beta2, eps, (hipStream_t)stream);
+  HIPCHK(hipGetLastError());
+  return RADULS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,591 @@
+// k_level.hip -- multi-workgroup levels of the MSD radix sort.
+//
+// One level splits every bucket of a list by its next digit (paper, Sec. 1:
+// a counting pass is a histogram traversal, the offsets of smaller digits,
+// and a distribution traversal; Sec. 3.2-3.3: the first pass and the passes
+// on big bins use all threads).  On the GPU a level is:
+//   k_prefix   tile ranges of the list's buckets
+//   k_hist     per-bucket digit histogram (LDS, wave-aggregated) and the OR of
+//              key XOR a reference key (which bits vary in the bucket)
+//   k_scan     per bucket: digit offsets, child buckets classified into the
+//              next list, the single-workgroup queue, the tiny queue or done
+//   k_scatter  stable tile ranking, decoupled look-back over tiles of the
+//              bucket, LDS staging by digit, coalesced writes
+#include "raduls_dev.hpp"
+#include "raduls_kernels.hpp"
+
+namespace rd {
+
+constexpr uint32_t LB_SPIN_LIMIT = 1u << 24;  // look-back waits this many polls at most
+
+__device__ __forceinline__ Bucket* level_list(const Plan& p, const Work& w, uint32_t level) {
+  return w.big + (uint64_t)level * p.cap_big;
+}
+__device__ __forceinline__ uint64_t* level_start(const Plan& p, const Work& w, uint32_t level) {
+  return w.tile_start + (uint64_t)level * (p.cap_big + 1);
+}
+
+// ---------------------------------------------------------------------------
+// Control-block reset and the look-back epoch of this sort.
+__global__ void k_init(Work w) {
+  uint32_t* epoch_counter = w.epoch_counter;
+  uint32_t* c = reinterpret_cast<uint32_t*>(w.ctl);
+  for (uint32_t i = threadIdx.x; i < sizeof(Ctl) / 4; i += blockDim.x) c[i] = 0;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t e = *epoch_counter + (LMAX + 1);
+    *epoch_counter = e;
+    w.ctl->epoch = e;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Appending buckets to the queues.  Classification of a bucket that still
+// needs work (Sec. 3.2: big bins above 2N/3T; Sec. 3.5: the smallest bins).
+__device__ __forceinline__ void push_big(const Plan& p, const Work& w, uint32_t level, const Bucket& b) {
+  uint32_t i = atomicAdd(&w.ctl->nbig[level], 1u);
+  if (i < p.cap_big) level_list(p, w, level)[i] = b;
+  else atomicOr(&w.ctl->overflow, 1u);
+}
+__device__ __forceinline__ void push_small(const Plan& p, const Work& w, const Bucket& b) {
+  uint32_t i = atomicAdd(&w.ctl->nsmall, 1u);
+  if (i < p.cap_small) w.small[i] = b;
+  else atomicOr(&w.ctl->overflow, 2u);
+}
+__device__ __forceinline__ void push_tiny(const Plan& p, const Work& w, uint64_t packed) {
+  uint32_t i = atomicAdd(&w.ctl->ntiny, 1u);
+  if (i < p.cap_tiny) w.tiny[i] = packed;
+  else atomicOr(&w.ctl->overflow, 4u);
+}
+__device__ __forceinline__ void push_copy(const Plan& p, const Work& w, const Bucket& b) {
+  uint32_t i = atomicAdd(&w.ctl->ncopy, 1u);
+  if (i < p.cap_copy) w.copy[i] = b;
+  else atomicOr(&w.ctl->overflow, 8u);
+}
+
+// Route a bucket (records [begin, begin+count) at resolved bit `bit`, in tmp
+// if `in_tmp`) to where it is finished.  `level` is the next list.
+__device__ void route_bucket(const Plan& p, const Work& w, uint32_t next_level, Bucket b, uint32_t kbits) {
+  bool in_tmp = b.flags & BF_TMP;
+  bool done = b.count <= 1 || b.bit >= kbits;
+  if (done) {
+    if (!in_tmp || b.count == 0) return;
+    if (b.count <= 63) push_tiny(p, w, pack_tiny(b.begin, (uint32_t)b.count, 1u, kbits));
+    else push_copy(p, w, b);
+    return;
+  }
+  if (b.count > p.t_big && next_level < p.lmax) {
+    push_big(p, w, next_level, b);
+  } else if (b.count <= TINY_MAX) {
+    push_tiny(p, w, pack_tiny(b.begin, (uint32_t)b.count, in_tmp ? 1u : 0u, b.bit));
+  } else {
+    push_small(p, w, b);
+  }
+}
+
+// The whole array as one bucket.
+__global__ void k_seed_single(Plan p, Work w) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (p.partition) {
+    Bucket b{0, p.n, p.n, p.partition_bit, 0u};
+    push_big(p, w, 0, b);
+    return;
+  }
+  Bucket b{0, p.n, p.n, 0u, 0u};
+  route_bucket(p, w, 0, b, 8 * p.key_bytes);
+}
+
+// Segment offsets must start at 0, never decrease and end at the total.
+__global__ void k_check_segments(Plan p, Work w, const uint64_t* off, uint32_t S) {
+  uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (i == 0 && (off[0] != 0 || off[S] != p.n)) atomicOr(&w.ctl->error, 1u);
+  if (i < S && off[i + 1] < off[i]) atomicOr(&w.ctl->error, 1u);
+}
+
+// Every segment is a bucket of its own (a batch of independent arrays).
+__global__ void k_seed_segments(Plan p, Work w, const uint64_t* off, uint32_t S) {
+  if (w.ctl->error) return;
+  uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  uint64_t a = off[s], c = off[s + 1] - a;
+  Bucket b{a, c, c, 0u, 0u};
+  route_bucket(p, w, 0, b, 8 * p.key_bytes);
+}
+
+// ---------------------------------------------------------------------------
+// Tile ranges of a list: start[i] = sum of ceil(count/tile) over entries < i.
+// One workgroup; also resets the list's tile ticket.
+__global__ void k_prefix(const Bucket* list, const uint32_t* nlist, uint64_t cap, uint64_t* start,
+                         uint64_t* total, uint32_t* ticket, uint32_t tile) {
+  __shared__ uint64_t part[WG];
+  uint32_t nb = min((uint64_t)*nlist, cap);
+  uint32_t t = threadIdx.x;
+  uint32_t per = (nb + WG - 1) / WG;
+  uint32_t lo = min(nb, t * per), hi = min(nb, lo + per);
+  uint64_t s = 0;
+  for (uint32_t i = lo; i < hi; i++) s += (list[i].count + tile - 1) / tile;
+  part[t] = s;
+  __syncthreads();
+  if (t == 0) {
+    uint64_t run = 0;
+    for (int i = 0; i < WG; i++) { uint64_t c = part[i]; part[i] = run; run += c; }
+    *total = run;
+    start[nb] = run;
+    if (ticket) *ticket = 0;
+  }
+  __syncthreads();
+  uint64_t run = part[t];
+  for (uint32_t i = lo; i < hi; i++) { start[i] = run; run += (list[i].count + tile - 1) / tile; }
+}
+
+// Zero the histogram and varying-bit words of a level's buckets.
+__global__ void k_clear_hist(Plan p, Work w, uint32_t level) {
+  uint32_t nb = min((uint64_t)w.ctl->nbig[level], p.cap_big);
+  uint64_t R = 1ull << p.d_big;
+  uint64_t total = (uint64_t)nb * R;
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < total;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    w.hist[i] = 0;
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < 2ull * nb;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    w.vary[i] = 0;
+}
+
+template <int RW, int DB>
+__global__ __launch_bounds__(WG) void k_hist(Plan p, Work w, uint32_t level, const uint8_t* rec0,
+                                             const uint8_t* rec1) {
+  constexpr uint32_t RMAX = 1u << DB;
+  constexpr uint32_t HB = 16;  // keys loaded per thread before they are counted
+  __shared__ uint32_t sh[RMAX];
+  __shared__ uint64_t sv[2 * NWAVES];
+  const Bucket* list = level_list(p, w, level);
+  const uint64_t* start = level_start(p, w, level);
+  uint32_t nb = min((uint64_t)w.ctl->nbig[level], p.cap_big);
+  uint64_t T = w.ctl->ntiles[level];
+  if (nb == 0 || T == 0) return;
+  uint64_t per = (T + gridDim.x - 1) / gridDim.x;
+  uint64_t t = blockIdx.x * per;
+  uint64_t t1 = min(T, t + per);
+  const KeyFmt kf = make_keyfmt(p.key_bytes);
+  const uint32_t lane = lane_id();
+  const uint32_t RS = 1u << p.d_big;
+  const uint32_t IPT = p.tile / WG;
+  while (t < t1) {
+    uint32_t b = find_entry(start, nb, t);
+    Bucket B = list[b];
+    uint64_t bt0 = start[b];
+    uint64_t tend = min(t1, start[b + 1]);
+    uint32_t d = min(p.d_big, kf.kbits - B.bit);
+    uint32_t shift = kf.kbits - B.bit - d;
+    uint32_t mask = (1u << d) - 1u;
+    const uint8_t* src = (B.flags & BF_TMP) ? rec1 : rec0;
+    Key ref = load_key<RW>(src, B.begin, kf);
+    for (uint32_t i = threadIdx.x; i < (1u << d); i += WG) sh[i] = 0;
+    __syncthreads();
+    uint64_t vlo = 0, vhi = 0;
+    uint64_t bend = B.begin + B.count;
+    for (; t < tend; t++) {
+      uint64_t r0 = B.begin + (t - bt0) * p.tile;
+      for (uint32_t j0 = 0; j0 < IPT; j0 += HB) {
+        Key kk[HB];
+#pragma unroll
+        for (uint32_t u = 0; u < HB; u++) {
+          uint64_t i = r0 + (uint64_t)(j0 + u) * WG + threadIdx.x;
+          kk[u] = (j0 + u < IPT && i < bend) ? load_key<RW>(src, i, kf) : ref;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < HB; u++) {
+          uint64_t i = r0 + (uint64_t)(j0 + u) * WG + threadIdx.x;
+          bool valid = j0 + u < IPT && i < bend;
+          vlo |= kk[u].lo ^ ref.lo;
+          vhi |= kk[u].hi ^ ref.hi;
+          uint32_t v = key_digit(kk[u], shift, mask);
+          uint64_t active = __ballot(valid);
+          uint64_t peers = match_digit(v, d, active);
+          if (valid && (uint32_t)(__ffsll((long long)peers) - 1) == lane)
+            atomicAdd(&sh[v], (uint32_t)__popcll(peers));
+        }
+      }
+    }
+    vlo = wave_or64(vlo);
+    vhi = wave_or64(vhi);
+    if (lane == 0) { sv[2 * (threadIdx.x / 64)] = vlo; sv[2 * (threadIdx.x / 64) + 1] = vhi; }
+    __syncthreads();
+    uint64_t* gh = w.hist + (uint64_t)b * RS;
+    for (uint32_t i = threadIdx.x; i < (1u << d); i += WG) {
+      uint32_t c = sh[i];
+      if (c) atomicAdd((unsigned long long*)&gh[i], (unsigned long long)c);
+    }
+    if (threadIdx.x == 0) {
+      uint64_t a = 0, c = 0;
+      for (int q = 0; q < NWAVES; q++) { a |= sv[2 * q]; c |= sv[2 * q + 1]; }
+      if (a) atomicOr((unsigned long long*)&w.vary[2 * b], (unsigned long long)a);
+      if (c) atomicOr((unsigned long long*)&w.vary[2 * b + 1], (unsigned long long)c);
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Per-bucket scan and classification.  One workgroup per list entry.
+template <int DB>
+__global__ __launch_bounds__(WG) void k_scan(Plan p, Work w, uint32_t level) {
+  constexpr uint32_t RMAX = 1u << DB;
+  __shared__ uint64_t off[RMAX];
+  __shared__ uint64_t part[WG];
+  Bucket* list = level_list(p, w, level);
+  uint32_t nb = min((uint64_t)w.ctl->nbig[level], p.cap_big);
+  const KeyFmt kf = make_keyfmt(p.key_bytes);
+  const uint32_t RS = 1u << p.d_big;
+  for (uint32_t b = blockIdx.x; b < nb; b += gridDim.x) {
+    Bucket B = list[b];
+    Key vary{w.vary[2 * b], w.vary[2 * b + 1]};
+    uint32_t d = min(p.d_big, kf.kbits - B.bit);
+    if (p.partition) {
+      // one stable pass for the caller: always move, report the counts
+      uint64_t* gh = w.hist + (uint64_t)b * RS;
+      uint32_t R = 1u << d;
+      if (w.counts_out)
+        for (uint32_t i = threadIdx.x; i < R; i += WG) w.counts_out[i] = gh[i];
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        uint64_t run = 0;
+        for (uint32_t i = 0; i < R; i++) { uint64_t c = gh[i]; gh[i] = run; run += c; }
+      }
+      __syncthreads();
+      continue;
+    }
+    if (vary.lo == 0 && vary.hi == 0) {
+      // every key equal: the bucket is finished where it lies
+      if (threadIdx.x == 0) {
+        list[b].flags = B.flags | BF_SKIP;
+        Bucket c = B;
+        c.bit = kf.kbits;
+        route_bucket(p, w, level + 1, c, kf.kbits);
+      }
+      __syncthreads();
+      continue;
+    }
+    uint32_t lead = common_prefix_bits(vary, kf.kbits);
+    if (lead >= B.bit + d) {
+      // the digit is the same for all keys: skip the move, resolve the
+      // shared bits and split on the first differing digit next level
+      if (threadIdx.x == 0) {
+        list[b].flags = B.flags | BF_SKIP;
+        Bucket c = B;
+        c.bit = lead;
+        route_bucket(p, w, level + 1, c, kf.kbits);
+      }
+      __syncthreads();
+      continue;
+    }
+    uint64_t* gh = w.hist + (uint64_t)b * RS;
+    uint32_t R = 1u << d;
+    uint32_t per = (R + WG - 1) / WG;
+    uint32_t lo = min(R, threadIdx.x * per), hi = min(R, lo + per);
+    uint64_t s = 0;
+    for (uint32_t i = lo; i < hi; i++) { off[i] = gh[i]; s += off[i]; }
+    part[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint64_t run = 0;
+      for (int i = 0; i < WG; i++) { uint64_t c = part[i]; part[i] = run; run += c; }
+    }
+    __syncthreads();
+    uint64_t run = part[threadIdx.x];
+    for (uint32_t i = lo; i < hi; i++) {
+      uint64_t c = off[i];
+      gh[i] = run;  // digit base, read by the scatter
+      if (c) {
+        Bucket ch;
+        ch.begin = B.begin + run;
+        ch.count = c;
+        ch.parent = B.count;
+        ch.bit = B.bit + d;
+        ch.flags = (B.flags & BF_TMP) ^ BF_TMP;
+        route_bucket(p, w, level + 1, ch, kf.kbits);
+      }
+      run += c;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Stable scatter of one level with decoupled look-back.
+//
+// A tile is `tile` consecutive records of one bucket; tiles are claimed in
+// order through an atomic ticket, so every tile a workgroup waits for
+// belongs to a workgroup that started earlier.  Within a tile, wave q owns
+// records [q*tile/4, (q+1)*tile/4) and takes them 64 at a time; a record's
+// rank among equal digits is (count in earlier waves) + (count in earlier
+// rounds of its wave) + (lanes of its round with the same digit below it), so
+// the tile keeps input order within each digit.  The tile publishes its
+// per-digit counts, adds up its predecessors' counts by look-back, stages the
+// records in LDS ordered by digit, and writes each digit's run contiguously.
+template <int RW, int DB>
+__global__ __launch_bounds__(WG) void k_scatter(Plan p, Work w, uint32_t level, const uint8_t* rec0,
+                                                uint8_t* rec0w, const uint8_t* rec1, uint8_t* rec1w) {
+  constexpr uint32_t RMAX = 1u << DB;
+  constexpr uint32_t IPT_MAX = RW >= 2 ? 64 / RW : 32;  // at most 64 words of records per thread
+  extern __shared__ __align__(16) uint32_t stage[];
+  __shared__ uint32_t wcnt[NWAVES * RMAX];
+  __shared__ uint32_t toff[RMAX + 1];
+  __shared__ uint32_t tcnt[RMAX];
+  __shared__ uint64_t gbase[RMAX];
+  __shared__ uint32_t sscan[NWAVES + 1];
+  __shared__ uint64_t sticket;
+  __shared__ uint32_t sb;
+
+  const Bucket* list = level_list(p, w, level);
+  const uint64_t* start = level_start(p, w, level);
+  uint32_t nb = min((uint64_t)w.ctl->nbig[level], p.cap_big);
+  uint64_t T = w.ctl->ntiles[level];
+  if (nb == 0 || T == 0) return;
+  const KeyFmt kf = make_keyfmt(p.key_bytes);
+  const uint32_t lane = lane_id();
+  const uint32_t wave = threadIdx.x / 64;
+  const uint32_t RS = 1u << p.d_big;
+  const uint32_t IPT = p.tile / WG;
+  const uint32_t per_wave = p.tile / NWAVES;
+  const uint64_t epoch = (uint64_t)((w.ctl->epoch + level) & 0x3FFFFFu) << LB_EPOCH_SHIFT;
+  const bool nt = p.nontemporal != 0;
+
+  for (;;) {
+    if (threadIdx.x == 0) {
+      uint64_t tk = atomicAdd(&w.ctl->ticket[level], 1u);
+      sticket = tk;
+      sb = tk < T ? find_entry(start, nb, tk) : 0;
+    }
+    __syncthreads();
+    uint64_t ticket = sticket;
+    uint32_t b = sb;
+    __syncthreads();
+    if (ticket >= T) break;
+    Bucket B = list[b];
+    if (B.flags & BF_SKIP) continue;
+    uint64_t ti = ticket - start[b];
+    uint64_t r0 = B.begin + ti * p.tile;
+    uint64_t bend = B.begin + B.count;
+    uint32_t cnt = (uint32_t)min((uint64_t)p.tile, bend - r0);
+    uint32_t d = min(p.d_big, kf.kbits - B.bit);
+    uint32_t R = 1u << d;
+    uint32_t shift = kf.kbits - B.bit - d;
+    uint32_t mask = R - 1u;
+    const uint8_t* src = (B.flags & BF_TMP) ? rec1 : rec0;
+    uint8_t* dst = (B.flags & BF_TMP) ? rec0w : rec1w;
+
+    for (uint32_t i = threadIdx.x; i < NWAVES * R; i += WG) wcnt[(i / R) * RMAX + (i % R)] = 0;
+    __syncthreads();
+
+    Rec<RW> rec[IPT_MAX];
+    uint32_t dg[IPT_MAX];
+    uint32_t rk[IPT_MAX];
+    uint64_t wbase = r0 + (uint64_t)wave * per_wave;
+#pragma unroll
+    for (uint32_t j = 0; j < IPT_MAX; j++) {
+      if (j < IPT) {
+        uint64_t i = wbase + (uint64_t)j * 64 + lane;
+        if (i < bend) rec[j] = load_rec<RW>(src, i);
+      }
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < IPT_MAX; j++) {
+      if (j < IPT) {
+        uint64_t i = wbase + (uint64_t)j * 64 + lane;
+        bool valid = i < bend;
+        uint32_t v = valid ? key_digit(rec_key<RW>(rec[j], kf), shift, mask) : 0u;
+        uint64_t active = __ballot(valid);
+        uint64_t peers = match_digit(v, d, active);
+        uint32_t before = (uint32_t)__popcll(peers & lanemask_lt());
+        uint32_t basec = valid ? wcnt[wave * RMAX + v] : 0u;
+        dg[j] = v;
+        rk[j] = basec + before;
+        if (valid && before == 0) wcnt[wave * RMAX + v] = basec + (uint32_t)__popcll(peers);
+      }
+    }
+    __syncthreads();
+    for (uint32_t v = threadIdx.x; v < R; v += WG) {
+      uint32_t s = 0;
+#pragma unroll
+      for (int q = 0; q < NWAVES; q++) { uint32_t c = wcnt[q * RMAX + v]; wcnt[q * RMAX + v] = s; s += c; }
+      tcnt[v] = s;
+      toff[v] = s;
+    }
+    __syncthreads();
+    block_excl_scan_lds(toff, R, sscan);
+    // stage the records in LDS ordered by digit
+#pragma unroll
+    for (uint32_t j = 0; j < IPT_MAX; j++) {
+      if (j < IPT) {
+        uint64_t i = wbase + (uint64_t)j * 64 + lane;
+        if (i < bend) {
+          uint32_t pos = toff[dg[j]] + wcnt[wave * RMAX + dg[j]] + rk[j];
+          lds_put<RW>(stage, pos, rec[j]);
+        }
+      }
+    }
+    // decoupled look-back, one digit per thread
+    uint64_t* st = w.status + ticket * RS;
+    const uint64_t* dbase = w.hist + (uint64_t)b * RS;
+    for (uint32_t v = threadIdx.x; v < R; v += WG) {
+      uint64_t c = tcnt[v];
+      uint64_t excl = 0;
+      if (ti == 0) {
+        atomic_store_agent(&st[v], epoch | LB_INC | c);
+      } else {
+        atomic_store_agent(&st[v], epoch | LB_AGG | c);
+        uint64_t j = ticket - 1;
+        uint32_t spins = 0;
+        for (;;) {
+          uint64_t s = atomic_load_agent(&w.status[j * RS + v]);
+          bool ready = (s >> LB_EPOCH_SHIFT) == (epoch >> LB_EPOCH_SHIFT) && (s & LB_FLAGS) != 0;
+          if (!ready) {
+            if (++spins > LB_SPIN_LIMIT) { atomicOr(&w.ctl->error, 2u); break; }
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+          }
+          excl += s & LB_VAL;
+          if ((s & LB_FLAGS) == LB_INC) break;
+          j--;
+        }
+        atomic_store_agent(&st[v], epoch | LB_INC | (excl + c));
+      }
+      gbase[v] = B.begin + dbase[v] + excl - toff[v];
+    }
+    __syncthreads();
+    for (uint32_t q = threadIdx.x; q < cnt; q += WG) {
+      Rec<RW> r = lds_get<RW>(stage, q);
+      uint32_t v = key_digit(rec_key<RW>(r, kf), shift, mask);
+      store_rec<RW>(dst, gbase[v] + q, r, nt);
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Copy finished buckets that lie in tmp back to records (tile-parallel).
+template <int RW>
+__global__ __launch_bounds__(WG) void k_copy(Plan p, Work w, const uint8_t* tmp, uint8_t* records) {
+  __shared__ uint64_t sticket;
+  __shared__ uint32_t sb;
+  uint32_t nb = min((uint64_t)w.ctl->ncopy, p.cap_copy);
+  uint64_t T = w.ctl->copy_tiles;
+  if (nb == 0 || T == 0) return;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      uint64_t tk = atomicAdd(&w.ctl->copy_ticket, 1u);
+      sticket = tk;
+      sb = tk < T ? find_entry(w.copy_start, nb, tk) : 0;
+    }
+    __syncthreads();
+    uint64_t ticket = sticket;
+    uint32_t b = sb;
+    __syncthreads();
+    if (ticket >= T) break;
+    Bucket B = w.copy[b];
+    uint64_t r0 = B.begin + (ticket - w.copy_start[b]) * p.tile;
+    uint64_t r1 = min(B.begin + B.count, r0 + p.tile);
+    for (uint64_t i = r0 + threadIdx.x; i < r1; i += WG) store_rec<RW>(records, i, load_rec<RW>(tmp, i), false);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Order the single-workgroup queue by size class, largest first (Sec. 3.2:
+// the queue hands out the largest bins first).
+__global__ void k_class_count(Plan p, Work w) {
+  __shared__ uint32_t c[NCLASS];
+  for (uint32_t i = threadIdx.x; i < NCLASS; i += blockDim.x) c[i] = 0;
+  __syncthreads();
+  uint32_t ns = min((uint64_t)w.ctl->nsmall, p.cap_small);
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < ns; i += (uint64_t)gridDim.x * blockDim.x)
+    atomicAdd(&c[63 - __clzll(w.small[i].count)], 1u);
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < NCLASS; i += blockDim.x)
+    if (c[i]) atomicAdd(&w.ctl->class_count[i], c[i]);
+}
+
+__global__ void k_class_offsets(Work w) {
+  if (threadIdx.x != 0) return;
+  uint32_t run = 0;
+  for (int i = NCLASS - 1; i >= 0; i--) { uint32_t c = w.ctl->class_count[i]; w.ctl->class_count[i] = run; run += c; }
+}
+
+__global__ void k_class_scatter(Plan p, Work w) {
+  uint32_t ns = min((uint64_t)w.ctl->nsmall, p.cap_small);
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < ns; i += (uint64_t)gridDim.x * blockDim.x) {
+    Bucket b = w.small[i];
+    uint32_t pos = atomicAdd(&w.ctl->class_count[63 - __clzll(b.count)], 1u);
+    w.small_ord[pos] = b;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers.
+
+template <int RW>
+static void launch_level_rw(const Plan& p, const Work& w, uint32_t level, const uint8_t* rec0, uint8_t* rec0w,
+                            const uint8_t* rec1, uint8_t* rec1w, hipStream_t s) {
+  size_t stage = (size_t)p.tile * p.rec_bytes;
+  if (p.d_big <= 8) {
+    k_hist<RW, 8><<<p.grid_hist, WG, 0, s>>>(p, w, level, rec0, rec1);
+    k_scan<8><<<p.grid_clear, WG, 0, s>>>(p, w, level);
+    k_scatter<RW, 8><<<p.grid_scatter, WG, stage, s>>>(p, w, level, rec0, rec0w, rec1, rec1w);
+  } else {
+    k_hist<RW, 11><<<p.grid_hist, WG, 0, s>>>(p, w, level, rec0, rec1);
+    k_scan<11><<<p.grid_clear, WG, 0, s>>>(p, w, level);
+    k_scatter<RW, 11><<<p.grid_scatter, WG, stage, s>>>(p, w, level, rec0, rec0w, rec1, rec1w);
+  }
+}
+
+void launch_init(const Work& w, hipStream_t s) {
+  k_init<<<1, WG, 0, s>>>(w);
+}
+
+void launch_seed_single(const Plan& p, const Work& w, hipStream_t s) {
+  k_seed_single<<<1, 64, 0, s>>>(p, w);
+}
+
+void launch_seed_segments(const Plan& p, const Work& w, const uint64_t* off, uint32_t S, hipStream_t s) {
+  uint32_t g = (S + WG) / WG;
+  k_check_segments<<<g, WG, 0, s>>>(p, w, off, S);
+  k_seed_segments<<<g, WG, 0, s>>>(p, w, off, S);
+}
+
+void launch_level(const Plan& p, const Work& w, uint32_t level, void* records, void* tmp, hipStream_t s) {
+  k_prefix<<<1, WG, 0, s>>>(w.big + (uint64_t)level * p.cap_big, &w.ctl->nbig[level], p.cap_big,
+                            w.tile_start + (uint64_t)level * (p.cap_big + 1), &w.ctl->ntiles[level],
+                            &w.ctl->ticket[level], p.tile);
+  k_clear_hist<<<p.grid_clear, WG, 0, s>>>(p, w, level);
+  const uint8_t* r0 = (const uint8_t*)records;
+  const uint8_t* r1 = (const uint8_t*)tmp;
+  uint8_t* w0 = (uint8_t*)records;
+  uint8_t* w1 = (uint8_t*)tmp;
+  switch (p.rw) {
+#define RD_CASE(n) case n: launch_level_rw<n>(p, w, level, r0, w0, r1, w1, s); break;
+    RD_CASE(1) RD_CASE(2) RD_CASE(3) RD_CASE(4) RD_CASE(5) RD_CASE(6) RD_CASE(7) RD_CASE(8)
+    RD_CASE(9) RD_CASE(10) RD_CASE(11) RD_CASE(12) RD_CASE(13) RD_CASE(14) RD_CASE(15) RD_CASE(16)
+#undef RD_CASE
+    default: break;
+  }
+}
+
+void launch_order_small(const Plan& p, const Work& w, hipStream_t s) {
+  k_class_count<<<p.grid_clear, WG, 0, s>>>(p, w);
+  k_class_offsets<<<1, 64, 0, s>>>(w);
+  k_class_scatter<<<p.grid_clear, WG, 0, s>>>(p, w);
+}
+
+void launch_copy(const Plan& p, const Work& w, void* records, const void* tmp, hipStream_t s) {
+  k_prefix<<<1, WG, 0, s>>>(w.copy, &w.ctl->ncopy, p.cap_copy, w.copy_start, &w.ctl->copy_tiles,
+                            &w.ctl->copy_ticket, p.tile);
+  switch (p.rw) {
+#define RD_CASE(n) case n: k_copy<n><<<p.grid_scatter, WG, 0, s>>>(p, w, (const uint8_t*)tmp, (uint8_t*)records); break;
+    RD_CASE(1) RD_CASE(2) RD_CASE(3) RD_CASE(4) RD_CASE(5) RD_CASE(6) RD_CASE(7) RD_CASE(8)
+    RD_CASE(9) RD_CASE(10) RD_CASE(11) RD_CASE(12) RD_CASE(13) RD_CASE(14) RD_CASE(15) RD_CASE(16)
+#undef RD_CASE
+    default: break;
+  }
+}
+
+}  // namespace rd

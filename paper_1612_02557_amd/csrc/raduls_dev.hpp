@@ -1,0 +1,309 @@
+// raduls_dev.hpp -- device-side building blocks shared by the sort kernels.
+//
+// Records are rec_bytes = 4*RW bytes; the key is the little-endian unsigned
+// integer of the first key_bytes bytes (paper, Sec. 1: keys are strings of
+// base-R digits; Sec. 4: key followed by data).  A key is held as two 64-bit
+// words (lo = bytes 0..7, hi = bytes 8..15), masked to key_bytes.
+//
+// Digits are taken most significant first.  A bucket carries `bit`, the
+// number of leading key bits already resolved; its next digit of width d is
+// floor(key / 2^(KB - bit - d)) mod 2^d with KB = 8*key_bytes (the paper's
+// current_byte, Sec. 3.2-3.4, generalised to bit positions so that a bucket
+// can skip bits that all its keys share).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "raduls_plan.hpp"
+
+namespace rd {
+
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+typedef uint32_t v2u __attribute__((ext_vector_type(2)));
+
+constexpr int WG = 256;         // threads of every sort workgroup
+constexpr int NWAVES = WG / 64; // wavefronts per workgroup
+
+struct Key {
+  uint64_t lo, hi;
+};
+
+template <int RW>
+struct Rec {
+  uint32_t w[RW];
+};
+
+// ---- record access --------------------------------------------------------
+
+template <int RW>
+__device__ __forceinline__ Rec<RW> load_rec(const uint8_t* __restrict__ base, uint64_t i) {
+  Rec<RW> r;
+  const uint8_t* p = base + i * (uint64_t)(RW * 4);
+  if constexpr (RW % 4 == 0) {
+#pragma unroll
+    for (int j = 0; j < RW / 4; j++) {
+      v4u v = reinterpret_cast<const v4u*>(p)[j];
+      r.w[4 * j + 0] = v.x; r.w[4 * j + 1] = v.y; r.w[4 * j + 2] = v.z; r.w[4 * j + 3] = v.w;
+    }
+  } else if constexpr (RW % 2 == 0) {
+#pragma unroll
+    for (int j = 0; j < RW / 2; j++) {
+      v2u v = reinterpret_cast<const v2u*>(p)[j];
+      r.w[2 * j + 0] = v.x; r.w[2 * j + 1] = v.y;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < RW; j++) r.w[j] = reinterpret_cast<const uint32_t*>(p)[j];
+  }
+  return r;
+}
+
+template <int RW>
+__device__ __forceinline__ void store_rec(uint8_t* __restrict__ base, uint64_t i, const Rec<RW>& r,
+                                          bool nt) {
+  uint8_t* p = base + i * (uint64_t)(RW * 4);
+  if constexpr (RW % 4 == 0) {
+#pragma unroll
+    for (int j = 0; j < RW / 4; j++) {
+      v4u v = {r.w[4 * j + 0], r.w[4 * j + 1], r.w[4 * j + 2], r.w[4 * j + 3]};
+      v4u* q = reinterpret_cast<v4u*>(p) + j;
+      if (nt) __builtin_nontemporal_store(v, q); else *q = v;
+    }
+  } else if constexpr (RW % 2 == 0) {
+#pragma unroll
+    for (int j = 0; j < RW / 2; j++) {
+      v2u v = {r.w[2 * j + 0], r.w[2 * j + 1]};
+      v2u* q = reinterpret_cast<v2u*>(p) + j;
+      if (nt) __builtin_nontemporal_store(v, q); else *q = v;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < RW; j++) {
+      uint32_t* q = reinterpret_cast<uint32_t*>(p) + j;
+      if (nt) __builtin_nontemporal_store(r.w[j], q); else *q = r.w[j];
+    }
+  }
+}
+
+// LDS copies of records (word arrays, record i at words [i*RW, i*RW+RW)).
+template <int RW>
+__device__ __forceinline__ void lds_put(uint32_t* s, uint32_t i, const Rec<RW>& r) {
+  uint32_t* p = s + i * RW;
+  if constexpr (RW % 4 == 0) {
+#pragma unroll
+    for (int j = 0; j < RW / 4; j++)
+      reinterpret_cast<v4u*>(p)[j] = v4u{r.w[4 * j], r.w[4 * j + 1], r.w[4 * j + 2], r.w[4 * j + 3]};
+  } else if constexpr (RW % 2 == 0) {
+#pragma unroll
+    for (int j = 0; j < RW / 2; j++) reinterpret_cast<v2u*>(p)[j] = v2u{r.w[2 * j], r.w[2 * j + 1]};
+  } else {
+#pragma unroll
+    for (int j = 0; j < RW; j++) p[j] = r.w[j];
+  }
+}
+
+template <int RW>
+__device__ __forceinline__ Rec<RW> lds_get(const uint32_t* s, uint32_t i) {
+  Rec<RW> r;
+  const uint32_t* p = s + i * RW;
+  if constexpr (RW % 4 == 0) {
+#pragma unroll
+    for (int j = 0; j < RW / 4; j++) {
+      v4u v = reinterpret_cast<const v4u*>(p)[j];
+      r.w[4 * j] = v.x; r.w[4 * j + 1] = v.y; r.w[4 * j + 2] = v.z; r.w[4 * j + 3] = v.w;
+    }
+  } else if constexpr (RW % 2 == 0) {
+#pragma unroll
+    for (int j = 0; j < RW / 2; j++) {
+      v2u v = reinterpret_cast<const v2u*>(p)[j];
+      r.w[2 * j] = v.x; r.w[2 * j + 1] = v.y;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < RW; j++) r.w[j] = p[j];
+  }
+  return r;
+}
+
+// ---- keys and digits ------------------------------------------------------
+
+struct KeyFmt {
+  uint64_t mlo, mhi;  // masks keeping key bytes only
+  uint32_t kbits;     // 8 * key_bytes
+};
+
+__host__ __device__ inline KeyFmt make_keyfmt(uint32_t key_bytes) {
+  KeyFmt f;
+  f.kbits = 8 * key_bytes;
+  f.mlo = key_bytes >= 8 ? ~0ull : ((1ull << (8 * key_bytes)) - 1);
+  f.mhi = key_bytes <= 8 ? 0ull : (key_bytes >= 16 ? ~0ull : ((1ull << (8 * (key_bytes - 8))) - 1));
+  return f;
+}
+
+template <int RW>
+__device__ __forceinline__ Key rec_key(const Rec<RW>& r, const KeyFmt& f) {
+  uint64_t lo = r.w[0];
+  if constexpr (RW > 1) lo |= (uint64_t)r.w[1] << 32;
+  uint64_t hi = 0;
+  if constexpr (RW > 2) hi = r.w[2];
+  if constexpr (RW > 3) hi |= (uint64_t)r.w[3] << 32;
+  return Key{lo & f.mlo, hi & f.mhi};
+}
+
+// ---- key-only loads ------------------------------------------------------
+// Key-only loads (the histogram needs no payload).
+template <int RW>
+__device__ __forceinline__ Key load_key(const uint8_t* __restrict__ base, uint64_t i, const KeyFmt& f) {
+  const uint8_t* q = base + i * (uint64_t)(RW * 4);
+  uint64_t lo = 0, hi = 0;
+  if constexpr (RW % 2 == 0) {
+    v2u a = reinterpret_cast<const v2u*>(q)[0];
+    lo = a.x | ((uint64_t)a.y << 32);
+    if constexpr (RW >= 4) {
+      if (f.mhi) {
+        v2u b = reinterpret_cast<const v2u*>(q)[1];
+        hi = b.x | ((uint64_t)b.y << 32);
+      }
+    }
+  } else {
+    const uint32_t* u = reinterpret_cast<const uint32_t*>(q);
+    lo = u[0];
+    if constexpr (RW > 1) lo |= (uint64_t)u[1] << 32;
+    if constexpr (RW > 2) { if (f.mhi) hi = u[2]; }
+    if constexpr (RW > 3) { if (f.mhi) hi |= (uint64_t)u[3] << 32; }
+  }
+  return Key{lo & f.mlo, hi & f.mhi};
+}
+
+__device__ __forceinline__ uint64_t shr128_lo(Key k, uint32_t s) {
+  if (s >= 64) return k.hi >> (s - 64);
+  if (s == 0) return k.lo;
+  return (k.lo >> s) | (k.hi << (64 - s));
+}
+
+// Digit of width d whose lowest bit is `shift` (d <= 16).
+__device__ __forceinline__ uint32_t key_digit(Key k, uint32_t shift, uint32_t mask) {
+  return (uint32_t)shr128_lo(k, shift) & mask;
+}
+
+__device__ __forceinline__ bool key_less(Key a, Key b) {
+  return a.hi < b.hi || (a.hi == b.hi && a.lo < b.lo);
+}
+
+// Number of leading bits (of the KB-bit key) shared by all keys whose XOR
+// with a reference key OR-accumulates to v.  v == 0 means all keys equal.
+__device__ __forceinline__ uint32_t common_prefix_bits(Key v, uint32_t kbits) {
+  uint32_t lz;
+  if (v.hi) lz = __clzll(v.hi);
+  else if (v.lo) lz = 64 + __clzll(v.lo);
+  else return kbits;
+  return lz - (128 - kbits);
+}
+
+// ---- wavefront helpers ----------------------------------------------------
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  uint32_t l = lane_id();
+  return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+// Lanes of the wave (among `active`) holding the same digit value v (d bits).
+__device__ __forceinline__ uint64_t match_digit(uint32_t v, uint32_t d, uint64_t active) {
+  uint64_t peers = active;
+  for (uint32_t b = 0; b < d; b++) {
+    uint64_t bal = __ballot((v >> b) & 1u);
+    peers &= ((v >> b) & 1u) ? bal : ~bal;
+  }
+  return peers;
+}
+
+__device__ __forceinline__ uint64_t wave_or64(uint64_t x) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) x |= __shfl_xor(x, o);
+  return x;
+}
+
+__device__ __forceinline__ uint32_t wave_sum32(uint32_t x) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o);
+  return x;
+}
+
+// Exclusive prefix sum over a wave (Hillis-Steele on 64 lanes).
+__device__ __forceinline__ uint32_t wave_excl_scan(uint32_t x, uint32_t* total) {
+  uint32_t l = lane_id();
+  uint32_t inc = x;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t y = __shfl_up(inc, o);
+    if (l >= (uint32_t)o) inc += y;
+  }
+  *total = __shfl(inc, 63);
+  return inc - x;
+}
+
+// Block-wide exclusive scan of `count` uint32 values in LDS (in place),
+// count <= 16 * WG.  Uses `tmp` (NWAVES + 1 words of LDS).  Returns the total.
+__device__ __forceinline__ uint32_t block_excl_scan_lds(uint32_t* a, uint32_t count, uint32_t* tmp) {
+  const uint32_t t = threadIdx.x;
+  const uint32_t per = (count + WG - 1) / WG;  // contiguous run per thread
+  uint32_t lo = t * per, hi = min(lo + per, count);
+  uint32_t s = 0;
+  for (uint32_t i = lo; i < hi; i++) s += a[i];
+  uint32_t wtot;
+  uint32_t ex = wave_excl_scan(s, &wtot);
+  if (lane_id() == 0) tmp[t / 64] = wtot;
+  __syncthreads();
+  if (t == 0) {
+    uint32_t run = 0;
+    for (int w = 0; w < NWAVES; w++) { uint32_t c = tmp[w]; tmp[w] = run; run += c; }
+    tmp[NWAVES] = run;
+  }
+  __syncthreads();
+  uint32_t run = tmp[t / 64] + ex;
+  for (uint32_t i = lo; i < hi; i++) { uint32_t c = a[i]; a[i] = run; run += c; }
+  uint32_t total = tmp[NWAVES];
+  __syncthreads();
+  return total;
+}
+
+// ---- bucket descriptors ---------------------------------------------------
+
+// Tiny bucket (2..63 records) packed into one word:
+//   begin (40 bits) | count (6) << 40 | in-tmp (1) << 46 | bit (8) << 47
+__device__ __forceinline__ uint64_t pack_tiny(uint64_t begin, uint32_t count, uint32_t tmp, uint32_t bit) {
+  return begin | ((uint64_t)count << 40) | ((uint64_t)tmp << 46) | ((uint64_t)bit << 47);
+}
+
+// ---- look-back status words ----------------------------------------------
+// epoch (22 bits) << 42 | flag (2) << 40 | value (40): flag 1 = the tile's own
+// count (aggregate), flag 2 = the count of this and all earlier tiles of the
+// bucket (inclusive prefix).  A word whose epoch is not the current level's
+// is a leftover of an earlier level and reads as not ready.
+constexpr uint32_t LB_EPOCH_SHIFT = 42;
+constexpr uint64_t LB_AGG = 1ull << 40;
+constexpr uint64_t LB_INC = 2ull << 40;
+constexpr uint64_t LB_FLAGS = 3ull << 40;
+constexpr uint64_t LB_VAL = (1ull << 40) - 1;
+
+__device__ __forceinline__ uint64_t atomic_load_agent(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void atomic_store_agent(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Index of the list entry whose tile range holds `tile`: largest b with
+// start[b] <= tile, b < nb (start is non-decreasing).
+__device__ __forceinline__ uint32_t find_entry(const uint64_t* start, uint32_t nb, uint64_t tile) {
+  uint32_t lo = 0, hi = nb;  // answer in [lo, hi)
+  while (hi - lo > 1) {
+    uint32_t mid = (lo + hi) / 2;
+    if (start[mid] <= tile) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+}  // namespace rd

@@ -1,0 +1,30 @@
+// raduls_kernels.hpp -- host-side launchers of the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "raduls_plan.hpp"
+
+namespace rd {
+
+void launch_init(const Work& w, hipStream_t s);
+void launch_seed_single(const Plan& p, const Work& w, hipStream_t s);
+void launch_seed_segments(const Plan& p, const Work& w, const uint64_t* off, uint32_t S, hipStream_t s);
+void launch_level(const Plan& p, const Work& w, uint32_t level, void* records, void* tmp, hipStream_t s);
+void launch_order_small(const Plan& p, const Work& w, hipStream_t s);
+void launch_small(const Plan& p, const Work& w, void* records, void* tmp, hipStream_t s);
+void launch_copy(const Plan& p, const Work& w, void* records, const void* tmp, hipStream_t s);
+
+// scheduler network
+void launch_mlp_forward(const float* X, const float* theta, float* Y, uint32_t B, hipStream_t s);
+void launch_mlp_loss_grad(const float* X, const float* T, const float* M, const float* theta, float* grad,
+                          float* loss, float* scratch, uint32_t B, hipStream_t s);
+void launch_mlp_adam(float* theta, const float* grad, float* m, float* v, uint32_t t, float lr, float b1,
+                     float b2, float eps, hipStream_t s);
+
+// scratch floats the loss/gradient launcher needs for a batch
+size_t mlp_scratch_floats(uint32_t B);
+
+// LDS bytes the single-workgroup kernel needs for a plan
+uint32_t small_dynamic_lds(const Plan& p);
+
+}  // namespace rd

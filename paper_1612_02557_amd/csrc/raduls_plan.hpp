@@ -1,0 +1,94 @@
+// raduls_plan.hpp -- launch plan and workspace layout shared by host and kernels.
+#pragma once
+#include <stdint.h>
+
+#include "../../include/raduls.h"
+
+namespace rd {
+
+// Multi-workgroup list entry and queued single-workgroup bucket (32 bytes).
+struct Bucket {
+  uint64_t begin;   // first record
+  uint64_t count;   // records
+  uint64_t parent;  // records of the parent bucket (narrowing factor, Sec. 3.5)
+  uint32_t bit;     // leading key bits already resolved
+  uint32_t flags;   // bit 0: data in tmp; bit 1: skip the scatter (set by the scan)
+};
+constexpr uint32_t BF_TMP = 1u;
+constexpr uint32_t BF_SKIP = 2u;
+
+constexpr uint32_t LMAX = 20;        // multi-workgroup levels a plan may launch
+constexpr uint32_t TINY_MAX = 32;    // buckets this small go to one wavefront (Sec. 3.5: N <= 32)
+constexpr uint32_t SMALL_LDS_BYTES = 80 * 1024;  // dynamic LDS of the single-workgroup kernel
+constexpr uint32_t NCLASS = 40;      // size classes of the queued buckets (floor(log2(count)))
+
+// Device control block: list sizes, tickets, flags.  Cleared at the start of
+// every sort by the init kernel.
+struct Ctl {
+  uint32_t nbig[LMAX + 1];     // entries of each multi-workgroup list
+  uint32_t ticket[LMAX + 1];   // tile tickets of each level's scatter
+  uint64_t ntiles[LMAX + 1];   // tiles of each list (set by the prefix kernel)
+  uint32_t nsmall;             // queued single-workgroup buckets
+  uint32_t ntiny;              // queued tiny buckets
+  uint32_t ncopy;              // buckets to copy from tmp to records
+  uint32_t small_head;         // queue cursors of the persistent kernel
+  uint32_t tiny_head;
+  uint32_t class_count[NCLASS];
+  uint64_t copy_tiles;
+  uint32_t copy_ticket;
+  uint32_t error;              // bit 0: bad segment offsets, bit 1: look-back wait limit
+  uint32_t overflow;           // bit 0 big list, 1 small, 2 tiny, 3 copy, 4 stack
+  uint32_t epoch;              // look-back epoch of level 0 of this sort
+};
+
+struct Plan {
+  uint64_t n;              // records in all
+  uint64_t t_big;          // buckets above this are multi-workgroup (Sec. 3.2: 2N/3T)
+  uint64_t cap_big;        // entries per multi-workgroup list
+  uint64_t cap_small;      // entries of the single-workgroup queue
+  uint64_t cap_tiny;
+  uint64_t cap_copy;
+  uint64_t max_tiles;      // tiles of one level, upper bound
+  uint32_t rec_bytes, key_bytes, rw;
+  uint32_t d_big, d_block; // digit widths
+  uint32_t tile;           // records per tile of a multi-workgroup pass
+  uint32_t c_fin;          // largest bucket finished in LDS
+  uint32_t bitonic_max;
+  uint32_t nontemporal;
+  uint32_t lmax;           // levels launched
+  uint32_t grid_hist, grid_scatter, grid_small, grid_clear;
+  uint32_t stack_cap;      // entries per workgroup stack
+  uint32_t block_tile;     // records per tile of a one-workgroup pass
+  uint32_t wave_cap;       // largest bucket one wavefront finishes
+  uint32_t sched_mode, forced_proc;
+  uint32_t segmented;
+  uint32_t epoch;          // look-back epoch of level 0 (level l uses epoch + l)
+  uint32_t sample_period;  // counterfactual sampling period (0 = none)
+  uint32_t has_model;
+  uint32_t partition;      // 1: one level on one bucket, children not routed
+  uint32_t partition_bit;  // resolved bits of that bucket
+  uint64_t trace_cap;
+};
+
+// Device pointers of the workspace.
+struct Work {
+  Ctl* ctl;
+  Bucket* big;         // (LMAX + 1) lists of cap_big entries
+  uint64_t* tile_start;       // (LMAX + 1) x (cap_big + 1)
+  uint64_t* hist;             // cap_big x 2^d_big (per level, reused)
+  uint64_t* vary;             // cap_big x 2 (OR of key XOR reference key)
+  uint64_t* status;           // look-back words, max_tiles x 2^d_big
+  Bucket* small;       // cap_small
+  Bucket* small_ord;   // cap_small, ordered largest class first
+  uint64_t* tiny;             // cap_tiny packed tiny buckets
+  Bucket* copy;        // cap_copy
+  uint64_t* copy_start;       // cap_copy + 1
+  Bucket* stacks;      // grid_small x stack_cap
+  const float* model;         // scheduler network + feature normalisation, or null
+  raduls_trace_row* trace;
+  uint64_t* trace_count;
+  uint64_t* counts_out;       // partition: histogram for the caller, or null
+  uint32_t* epoch_counter;    // look-back epochs handed out so far
+};
+
+}  // namespace rd

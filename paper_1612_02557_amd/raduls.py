@@ -1,0 +1,301 @@
+"""ctypes binding of ``libraduls.so`` (argument marshalling only).
+
+Every operation runs in the library's HIP kernels; torch tensors only carry
+device memory and the current stream.  If the library is not built, loading
+raises ``RuntimeError`` -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import struct
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libraduls.so")
+
+OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED, EMODEL, EDEVICE = 0, -1, -2, -3, -4, -5, -6
+PROC_RADIX, PROC_LSD, PROC_BITONIC, PROC_RANK, PROC_BIG = 0, 1, 2, 3, 4
+SCHED_HEURISTIC, SCHED_LEARNED, SCHED_FORCED = 0, 1, 2
+MLP_F, MLP_H, MLP_P = 9, 32, 3
+MLP_PARAMS = MLP_F * MLP_H + MLP_H + MLP_H * MLP_H + MLP_H + MLP_P * MLP_H + MLP_P
+
+_vp = ctypes.c_void_p
+_u32 = ctypes.c_uint32
+_u64 = ctypes.c_uint64
+_i32 = ctypes.c_int
+_f32 = ctypes.c_float
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [
+        ("big_digit_bits", _u32),
+        ("block_digit_bits", _u32),
+        ("tile_records", _u32),
+        ("lds_finish_max", _u32),
+        ("bitonic_max", _u32),
+        ("workgroups_per_cu", _u32),
+        ("big_min", _u64),
+        ("nontemporal", _u32),
+        ("reserved", _u32),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+class TraceRow(ctypes.Structure):
+    _fields_ = [
+        ("features", ctypes.c_float * 9),
+        ("chosen", _u32),
+        ("count", _u32),
+        ("observed", _u32),
+        ("time_ticks", _u32 * 3),
+        ("flags", _u32),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("last_ms", ctypes.c_double),
+        ("last_records", _u64),
+        ("last_levels", _u32),
+        ("sched_mode", _u32),
+        ("workspace_bytes", _u64),
+        ("model_params", _u64),
+        ("graph_cache_entries", _u64),
+    ]
+
+
+TRACE_ROW_BYTES = ctypes.sizeof(TraceRow)
+
+_SIGS = {
+    "raduls_sort": (_i32, [_vp, _vp, _u64, _u32, _u32, _vp]),
+    "raduls_sort_segmented": (_i32, [_vp, _vp, _vp, _u32, _u64, _u32, _u32, _vp]),
+    "raduls_partition": (_i32, [_vp, _vp, _u64, _u32, _u32, _u32, _u32, _vp, _vp]),
+    "raduls_sync_check": (_i32, [_vp]),
+    "raduls_set_scheduler": (_i32, [_i32, _i32]),
+    "raduls_get_scheduler": (_i32, [ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
+    "raduls_load_model": (_i32, [_vp, ctypes.c_size_t]),
+    "raduls_unload_model": (_i32, []),
+    "raduls_set_tuning": (_i32, [ctypes.POINTER(Tuning)]),
+    "raduls_get_tuning": (_i32, [ctypes.POINTER(Tuning)]),
+    "raduls_default_tuning": (_i32, [_u32, _u32, _u64, ctypes.POINTER(Tuning)]),
+    "raduls_set_trace": (_i32, [_vp, _u64, _u32]),
+    "raduls_trace_count": (_i32, [ctypes.POINTER(_u64), _vp]),
+    "raduls_get_stats": (_i32, [ctypes.POINTER(Stats)]),
+    "raduls_set_timing": (_i32, [_i32]),
+    "raduls_workspace_bytes": (ctypes.c_size_t, [_u64, _u32, _u32]),
+    "raduls_status_string": (ctypes.c_char_p, [_i32]),
+    "raduls_last_error_message": (ctypes.c_char_p, []),
+    "raduls_release": (None, []),
+    "raduls_mlp_forward": (_i32, [_vp, _vp, _vp, _u32, _vp]),
+    "raduls_mlp_loss_grad": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _u32, _vp]),
+    "raduls_mlp_adam": (_i32, [_vp, _vp, _vp, _vp, _u32, _f32, _f32, _f32, _f32, _vp]),
+}
+
+EXPORTS = tuple(_SIGS)
+
+_lib = None
+
+
+class RadulsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+def lib():
+    """The loaded library (raises RuntimeError if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != OK:
+        msg = lib().raduls_last_error_message().decode(errors="replace")
+        raise RadulsError(rc, msg or lib().raduls_status_string(rc).decode())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _records(t):
+    import torch
+    if t.dtype != torch.uint8 or t.dim() != 2 or not t.is_contiguous() or not t.is_cuda:
+        raise ValueError("records must be a contiguous CUDA uint8 tensor of shape (n, rec_bytes)")
+    return t
+
+
+def sort(records, key_bytes: int, tmp=None, stream=None):
+    """Sort ``records`` (uint8 [n, rec_bytes] on the GPU) in place by key."""
+    import torch
+    records = _records(records)
+    n, r = records.shape
+    if tmp is None:
+        tmp = torch.empty_like(records)
+    _check(lib().raduls_sort(records.data_ptr(), tmp.data_ptr(), n, r, key_bytes, _stream(stream)))
+    return records
+
+
+def sort_ptr(records_ptr: int, tmp_ptr: int, n: int, rec_bytes: int, key_bytes: int, stream: int) -> int:
+    """Raw call returning the status code (for argument-error tests)."""
+    return lib().raduls_sort(records_ptr, tmp_ptr, n, rec_bytes, key_bytes, stream)
+
+
+def sort_segmented(records, offsets, key_bytes: int, tmp=None, stream=None):
+    """Sort each segment [offsets[s], offsets[s+1]) of ``records`` independently.
+
+    ``offsets`` is a CUDA int64/uint64 tensor of num_segs + 1 entries.
+    """
+    import torch
+    records = _records(records)
+    n, r = records.shape
+    if tmp is None:
+        tmp = torch.empty_like(records)
+    if not offsets.is_cuda or offsets.element_size() != 8 or not offsets.is_contiguous():
+        raise ValueError("offsets must be a contiguous 8-byte CUDA tensor")
+    S = offsets.numel() - 1
+    _check(lib().raduls_sort_segmented(records.data_ptr(), tmp.data_ptr(), offsets.data_ptr(), S, n, r,
+                                       key_bytes, _stream(stream)))
+    return records
+
+
+def partition(inp, out, key_bytes: int, shift: int, bits: int, counts=None, stream=None):
+    """One stable counting pass on the digit (shift, bits); ``counts`` (CUDA int64 [2**bits]) optional."""
+    inp = _records(inp)
+    out = _records(out)
+    n, r = inp.shape
+    cp = counts.data_ptr() if counts is not None else None
+    _check(lib().raduls_partition(inp.data_ptr(), out.data_ptr(), n, r, key_bytes, shift, bits, cp,
+                                  _stream(stream)))
+    return out
+
+
+def sync_check(stream=None):
+    _check(lib().raduls_sync_check(_stream(stream)))
+
+
+def set_scheduler(mode: int, forced_proc: int = 0):
+    _check(lib().raduls_set_scheduler(mode, forced_proc))
+
+
+def get_scheduler():
+    m, f = _i32(), _i32()
+    _check(lib().raduls_get_scheduler(ctypes.byref(m), ctypes.byref(f)))
+    return m.value, f.value
+
+
+def model_blob(theta, mean, scale) -> bytes:
+    """Serialise a network (flat parameters, feature means and scales)."""
+    import numpy as np
+    theta = np.asarray(theta, dtype=np.float32).ravel()
+    mean = np.asarray(mean, dtype=np.float32).ravel()
+    scale = np.asarray(scale, dtype=np.float32).ravel()
+    if theta.size != MLP_PARAMS or mean.size != MLP_F or scale.size != MLP_F:
+        raise ValueError("wrong parameter or feature-normalisation size")
+    body = b"RDLSMLP1" + struct.pack("<3I", MLP_F, MLP_H, MLP_P) + theta.tobytes() + mean.tobytes() + scale.tobytes()
+    return body + struct.pack("<I", fnv1a(body))
+
+
+def fnv1a(b: bytes) -> int:
+    h = 2166136261
+    for x in b:
+        h ^= x
+        h = (h * 16777619) & 0xFFFFFFFF
+    return h
+
+
+def load_model(blob: bytes):
+    buf = ctypes.create_string_buffer(blob, len(blob))
+    _check(lib().raduls_load_model(ctypes.cast(buf, _vp), len(blob)))
+
+
+def load_model_raw(blob: bytes) -> int:
+    buf = ctypes.create_string_buffer(blob, len(blob))
+    return lib().raduls_load_model(ctypes.cast(buf, _vp), len(blob))
+
+
+def unload_model():
+    _check(lib().raduls_unload_model())
+
+
+def default_tuning(rec_bytes: int, key_bytes: int, n: int) -> Tuning:
+    t = Tuning()
+    _check(lib().raduls_default_tuning(rec_bytes, key_bytes, n, ctypes.byref(t)))
+    return t
+
+
+def set_tuning(t: Tuning | None):
+    _check(lib().raduls_set_tuning(ctypes.byref(t) if t is not None else None))
+
+
+def get_tuning() -> Tuning | None:
+    t = Tuning()
+    rc = lib().raduls_get_tuning(ctypes.byref(t))
+    return t if rc == OK else None
+
+
+def set_trace(rows_tensor=None, sample_period: int = 0):
+    """Trace into a CUDA uint8 tensor of capacity * 64 bytes (None: off)."""
+    if rows_tensor is None:
+        _check(lib().raduls_set_trace(None, 0, 0))
+        return
+    cap = rows_tensor.numel() * rows_tensor.element_size() // TRACE_ROW_BYTES
+    _check(lib().raduls_set_trace(rows_tensor.data_ptr(), cap, sample_period))
+
+
+def trace_count(stream=None) -> int:
+    c = _u64()
+    _check(lib().raduls_trace_count(ctypes.byref(c), _stream(stream)))
+    return c.value
+
+
+def get_stats() -> Stats:
+    s = Stats()
+    _check(lib().raduls_get_stats(ctypes.byref(s)))
+    return s
+
+
+def set_timing(on: bool):
+    _check(lib().raduls_set_timing(1 if on else 0))
+
+
+def workspace_bytes(n: int, rec_bytes: int, key_bytes: int) -> int:
+    return lib().raduls_workspace_bytes(n, rec_bytes, key_bytes)
+
+
+def status_string(code: int) -> str:
+    return lib().raduls_status_string(code).decode()
+
+
+def release():
+    lib().raduls_release()
+
+
+def mlp_forward(X, theta, Y, stream=None):
+    _check(lib().raduls_mlp_forward(X.data_ptr(), theta.data_ptr(), Y.data_ptr(), X.shape[0], _stream(stream)))
+
+
+def mlp_loss_grad(X, T, M, theta, grad, loss, stream=None):
+    _check(lib().raduls_mlp_loss_grad(X.data_ptr(), T.data_ptr(), M.data_ptr(), theta.data_ptr(), grad.data_ptr(),
+                                      loss.data_ptr(), X.shape[0], _stream(stream)))
+
+
+def mlp_adam(theta, grad, m, v, t: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check(lib().raduls_mlp_adam(theta.data_ptr(), grad.data_ptr(), m.data_ptr(), v.data_ptr(), t, lr, beta1, beta2,
+                                 eps, _stream(stream)))

@@ -1,0 +1,150 @@
+"""GPU parity: the HIP sort against the oracle, byte for byte."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_util import first_diff, note, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def R():
+    import torch
+    from paper_1612_02557_amd import raduls
+    assert torch.cuda.is_available()
+    raduls.set_scheduler(raduls.SCHED_HEURISTIC)
+    raduls.set_tuning(None)
+    return raduls
+
+
+def gpu_sort(R, host, k):
+    import torch
+    dev = to_dev(host)
+    R.sort(dev, k)
+    R.sync_check()
+    torch.cuda.synchronize()
+    return dev.cpu().numpy()
+
+
+def check(R, host, k, label):
+    note(label)
+    got = gpu_sort(R, host, k)
+    want = oracle.sort(host, k)
+    assert np.array_equal(got, want), f"{label}: {first_diff(got, want)}"
+
+
+SIZES = [2, 3, 31, 32, 33, 63, 64, 65, 100, 255, 256, 257, 1000, 2047, 2048, 2049, 4095, 4096, 4097,
+         10000, 65535, 65536, 65537, 100_000, 1 << 20, 3_000_001]
+
+
+@pytest.mark.parametrize("n", SIZES)
+def test_uniform_16_8_sizes(R, n):
+    host = synth.generate(synth.Spec(n=n, rec_bytes=16, key_bytes=8, dist="uniform", seed=1))
+    check(R, host, 8, f"uniform r=16 k=8 n={n}")
+
+
+@pytest.mark.parametrize("dist", ["zipf", "prefix", "mix"])
+@pytest.mark.parametrize("n", [5000, 200_000, 2_000_003])
+def test_distributions(R, dist, n):
+    host = synth.generate(synth.Spec(n=n, rec_bytes=16, key_bytes=8, dist=dist, seed=3))
+    check(R, host, 8, f"{dist} r=16 k=8 n={n}")
+
+
+@pytest.mark.parametrize("r,k", [(8, 8), (16, 16), (32, 8), (32, 16), (4, 1), (4, 4), (12, 3), (20, 5),
+                                 (64, 16), (24, 16), (8, 2), (48, 12), (60, 9)])
+@pytest.mark.parametrize("n", [777, 70_001, 1_000_000])
+def test_record_shapes(R, r, k, n):
+    dist = "uniform" if k in (8, 16) else "bytes"
+    host = synth.generate(synth.Spec(n=n, rec_bytes=r, key_bytes=k, dist=dist, payload="random", seed=5))
+    check(R, host, k, f"{dist} r={r} k={k} n={n}")
+
+
+@pytest.mark.parametrize("r,k", [(16, 16), (32, 16)])
+@pytest.mark.parametrize("dist", ["zipf", "prefix", "mix"])
+def test_wide_keys_skewed(R, r, k, dist):
+    host = synth.generate(synth.Spec(n=300_000, rec_bytes=r, key_bytes=k, dist=dist, payload="random", seed=8))
+    check(R, host, k, f"{dist} r={r} k={k} n=300000")
+
+
+def _records_with_keys(keys, r=16):
+    n = len(keys)
+    rec = np.zeros((n, r), dtype=np.uint8)
+    rec[:, :8] = np.asarray(keys, dtype="<u8").view(np.uint8).reshape(n, 8)
+    rec[:, 8:16] = np.arange(n, dtype="<u8").view(np.uint8).reshape(n, 8)
+    return rec
+
+
+@pytest.mark.parametrize("n", [50, 5000, 300_000])
+def test_adversarial(R, n, rng):
+    cases = {
+        "all_equal": np.full(n, 0xDEADBEEF, dtype=np.uint64),
+        "sorted": np.sort(rng.integers(0, 2**63, n, dtype=np.uint64)),
+        "reverse": np.sort(rng.integers(0, 2**63, n, dtype=np.uint64))[::-1].copy(),
+        "two_values": rng.choice(np.array([3, 2**63 + 5], dtype=np.uint64), n),
+        "prefix56": (np.uint64(0xABCDEF12345678) << np.uint64(8)) | rng.integers(0, 256, n, dtype=np.uint64),
+        "prefix40": (np.uint64(0xABCDEF1234) << np.uint64(24)) | rng.integers(0, 2**24, n, dtype=np.uint64),
+        "low_bits_only": rng.integers(0, 16, n, dtype=np.uint64),
+        "one_giant": np.where(rng.random(n) < 0.9, np.uint64(77), rng.integers(0, 2**64 - 1, n, dtype=np.uint64)),
+        "max_keys": np.full(n, 2**64 - 1, dtype=np.uint64) - rng.integers(0, 3, n, dtype=np.uint64),
+    }
+    for name, keys in cases.items():
+        check(R, _records_with_keys(keys), 8, f"adversarial {name} n={n}")
+
+
+def test_empty_and_single(R):
+    import torch
+    for n in (0, 1):
+        note(f"n={n}")
+        host = synth.generate(synth.Spec(n=max(n, 1), rec_bytes=16, key_bytes=8, seed=2))[:n]
+        dev = torch.zeros((n, 16), dtype=torch.uint8, device="cuda")
+        if n:
+            dev.copy_(to_dev(host))
+        R.sort(dev, 8)
+        torch.cuda.synchronize()
+        assert np.array_equal(dev.cpu().numpy(), host)
+
+
+@pytest.mark.parametrize("proc", ["RADIX", "LSD", "BITONIC"])
+@pytest.mark.parametrize("dist", ["uniform", "zipf", "mix"])
+def test_forced_procedures_same_bytes(R, proc, dist):
+    host = synth.generate(synth.Spec(n=400_000, rec_bytes=16, key_bytes=8, dist=dist, seed=13))
+    p = {"RADIX": R.PROC_RADIX, "LSD": R.PROC_LSD, "BITONIC": R.PROC_BITONIC}[proc]
+    R.set_scheduler(R.SCHED_FORCED, p)
+    try:
+        check(R, host, 8, f"forced {proc} {dist} n=400000")
+    finally:
+        R.set_scheduler(R.SCHED_HEURISTIC)
+
+
+TUNINGS = [
+    dict(big_digit_bits=4),
+    dict(big_digit_bits=6, block_digit_bits=5),
+    dict(big_digit_bits=11),
+    dict(block_digit_bits=3, lds_finish_max=256, bitonic_max=64),
+    dict(tile_records=256, big_min=4096),
+    dict(tile_records=1024, big_min=2048, workgroups_per_cu=1),
+    dict(nontemporal=1, workgroups_per_cu=4),
+]
+
+
+@pytest.mark.parametrize("ti", range(len(TUNINGS)))
+def test_tuning_invariance(R, ti):
+    host = synth.generate(synth.Spec(n=500_000, rec_bytes=16, key_bytes=8, dist="mix", seed=21))
+    t = R.default_tuning(16, 8, 500_000)
+    for kk, v in TUNINGS[ti].items():
+        setattr(t, kk, v)
+    R.set_tuning(t)
+    try:
+        check(R, host, 8, f"tuning {TUNINGS[ti]}")
+    finally:
+        R.set_tuning(None)
+
+
+def test_run_twice_identical(R):
+    host = synth.generate(synth.Spec(n=1_000_000, rec_bytes=16, key_bytes=8, dist="mix", seed=4))
+    note("run twice")
+    a = gpu_sort(R, host, 8)
+    b = gpu_sort(R, host, 8)
+    assert np.array_equal(a, b)
