@@ -1,0 +1,237 @@
+#!/usr/bin/env python3
+"""Benchmark: sorted records/s of the MI355X MSD radix sort.
+
+Workload (default): 2^30 records of 16 bytes -- 8-byte uniform random keys
+from a seeded counter-based generator and an 8-byte payload holding each
+record's original index -- sorted by raduls_sort on one GPU with the
+heuristic scheduler.  The input is generated on the device, kept as a
+pristine copy, and copied into the working buffer before every step
+(outside the timed region), so every timed step sorts the same unsorted
+input that is already resident in HBM.
+
+Prints one JSON line (see the design doc for the fields).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0   # MI355X HBM3E, published peak
+METRIC = "sorted records/s and % of HBM roofline, 16-byte records, 1 MI355X; learned vs plain"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def model_bytes_per_record(n: int, r: int) -> float:
+    """Algorithmic bytes per record of the method: r * (3 + 2P).
+
+    One histogram read of the input, P multi-level partition passes of one
+    read and one write each (the next level's histogram is counted with its
+    pass), and one read plus one write by the LDS finishing sort; P is the
+    number of 11-bit partition passes that bring buckets to the LDS
+    finishing capacity of 64 KiB / r records.
+    """
+    import math
+    cap = 65536 // r
+    if n <= cap:
+        return 2.0 * r
+    P = math.ceil(math.log2(n / cap) / 11)
+    return float(r * (3 + 2 * P))
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    cs = os.path.join(ROOT, "paper_1612_02557_amd", "csrc")
+    for f in sorted(os.listdir(cs)):
+        if f.endswith((".hip", ".hpp", ".cpp")):
+            with open(os.path.join(cs, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str, workload: str):
+    """Measured HBM bytes per launch from committed counter runs, if still current."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    e = t.get(f"{kernel}|{workload}")
+    if not e or e.get("source_hash") != kernel_source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def cpu_baseline(pristine, key_bytes: int, sample_log2: int):
+    import numpy as np
+
+    import oracle
+    ns = min(pristine.shape[0], 1 << sample_log2)
+    host = pristine[:ns].cpu().numpy().copy()
+    cores = os.cpu_count() or 1
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit():
+        cores = max(1, min(cores, int(env)))
+    oracle.lib()
+    t0 = time.perf_counter()
+    oracle.sort_ref.sort_inplace(host, key_bytes, cores)
+    dt = time.perf_counter() - t0
+    k = host[:, :8].copy().view("<u8").ravel()
+    assert bool(np.all(k[:-1] <= k[1:])), "oracle output not sorted"
+    return {"value": ns / dt, "unit": "records/s", "cores": cores, "kind": "oracle",
+            "sample": f"first 2^{sample_log2} records of the benchmark input, stable LSD byte-wise counting sort "
+                      f"in {cores} threads, {dt:.2f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--log2n", type=int, default=30)
+    ap.add_argument("--rec-bytes", type=int, default=16)
+    ap.add_argument("--key-bytes", type=int, default=8)
+    ap.add_argument("--dist", default="uniform")
+    ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-sample-log2", type=int, default=26)
+    ap.add_argument("--phases", type=int, default=1, help="1: per-phase events during the timed steps")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              f"(the batched and single-array paths are single-GPU; see DESIGN.md for sharding)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import synth
+    from paper_1612_02557_amd import raduls
+    from synth import device as sdev
+    from tests.gpu_util import exact_index_check
+
+    raduls.lib()
+    n = 1 << args.log2n
+    r, k = args.rec_bytes, args.key_bytes
+    spec = synth.Spec(n=n, rec_bytes=r, key_bytes=k, dist=args.dist, payload="index", seed=args.seed)
+    log(f"generating {n} x {r}-byte records ({args.dist}) on the device")
+    pristine = sdev.generate(spec)
+    rec = torch.empty_like(pristine)
+    tmp = torch.empty_like(pristine)
+    torch.cuda.synchronize()
+    raduls.set_scheduler(raduls.SCHED_HEURISTIC)
+    raduls.set_timing(2 if args.phases else 1)
+
+    def step():
+        rec.copy_(pristine)
+        torch.cuda.synchronize()
+        raduls.sort(rec, k, tmp)
+        torch.cuda.synchronize()
+        return raduls.get_stats().last_ms
+
+    for w in range(args.warmup):
+        ms = step()
+        log(f"warmup {w}: {ms:.3f} ms")
+    times, phase_acc = [], {}
+    wall0 = time.perf_counter()
+    for s in range(args.steps):
+        ms = step()
+        times.append(ms)
+        if args.phases:
+            for name, v in raduls.phase_times().items():
+                phase_acc.setdefault(name, []).append(v)
+        log(f"step {s}: {ms:.3f} ms")
+    wall = time.perf_counter() - wall0
+    work = raduls.last_work()
+    ms_per_step = statistics.mean(times)
+    value = n / (ms_per_step / 1e3)
+
+    verified = None
+    if r == 16 and k == 8:
+        err = exact_index_check(rec, pristine)
+        verified = err is None
+        if err:
+            log(f"VERIFICATION FAILED: {err}")
+    try:
+        raduls.sync_check()
+    except raduls.RadulsError as e:
+        log(f"device check failed: {e}")
+        verified = False
+
+    # per-pass algorithmic bytes and rates
+    passes = []
+    for l, (n_in, n_moved) in enumerate(work["levels"]):
+        for kind, recs, mult in (("hist", n_in, 1), ("scatter", n_moved, 2)):
+            name = f"L{l}.{kind}"
+            if name in phase_acc:
+                t = statistics.mean(phase_acc[name])
+                b = mult * r * recs
+                passes.append({"phase": name, "kernel": f"k_{kind}", "ms": t, "records": recs, "alg_bytes": b,
+                               "GBps": b / t / 1e6 if t > 0 else None})
+    if "small" in phase_acc:
+        t = statistics.mean(phase_acc["small"])
+        recs = work["small"] + work["tiny"]
+        b = 2 * r * recs
+        passes.append({"phase": "small", "kernel": "k_small", "ms": t, "records": recs, "alg_bytes": b,
+                       "GBps": b / t / 1e6 if t > 0 else None})
+    other = {nm: statistics.mean(v) for nm, v in phase_acc.items()
+             if not any(p["phase"] == nm for p in passes)}
+
+    roof = None
+    if passes:
+        dom = max(passes, key=lambda p: p["ms"])
+        wl = f"{args.dist}-2^{args.log2n}x{r}B"
+        tr = load_traffic(dom["kernel"], wl)
+        roof = {"bound": "hbm", "achieved": dom["GBps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": dom["GBps"] / HBM_PEAK_GBPS if dom["GBps"] else None, "traffic": tr,
+                "kernel": dom["kernel"], "phase": dom["phase"], "avg_launch_ms": dom["ms"],
+                "alg_bytes_per_launch": dom["alg_bytes"]}
+    bpr = model_bytes_per_record(n, r)
+    t_roof_ms = bpr * n / (HBM_PEAK_GBPS * 1e9) * 1e3
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "records/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64" if k == 8 else "u128",
+        "data": "synthetic",
+        "config": {"workload": f"sort 2^{args.log2n} records of {r} bytes, {args.dist} {k}-byte keys, "
+                               f"payload = original index (seed {args.seed})",
+                   "n": n, "rec_bytes": r, "key_bytes": k, "dist": args.dist, "seed": args.seed,
+                   "scheduler": "heuristic"},
+        "roofline": roof,
+        "e2e": {"model_bytes_per_record": bpr, "t_roof_ms": t_roof_ms, "frac": t_roof_ms / ms_per_step,
+                "model_GBps": bpr * n / (ms_per_step / 1e3) / 1e9},
+        "passes": passes,
+        "other_phases_ms": other,
+        "step_ms": times,
+        "timed_wall_s": wall,
+        "verified": verified,
+    }
+    del tmp, rec
+    torch.cuda.empty_cache()
+    if not args.no_cpu:
+        log("timing the CPU oracle on a sample")
+        out["cpu_baseline"] = cpu_baseline(pristine, k, args.cpu_sample_log2)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

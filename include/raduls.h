@@ -166,8 +166,22 @@ int raduls_set_trace(void* rows, uint64_t capacity, uint32_t sample_period);
 int raduls_trace_count(uint64_t* host_count, void* stream);
 
 int raduls_get_stats(raduls_stats* host_stats);
-/* 1: time every sort with events (raduls_get_stats().last_ms), 0: off. */
+/* 1: time every sort with events (raduls_get_stats().last_ms); 2: also time
+ * each launch group of raduls_sort (raduls_phase_times); 0: off. */
 int raduls_set_timing(int on);
+/* Device milliseconds of each launch group of the last raduls_sort run with
+ * timing mode 2, waiting for it: index 0 setup; for level l (0..19) 1+4l
+ * tile ranges and histogram reset, 2+4l histogram, 3+4l scan, 4+4l scatter;
+ * 81 queue ordering, 82 single-workgroup kernel, 83 copy-back.  `count`
+ * entries of host_ms are written (84 cover every phase). */
+#define RADULS_PHASES 84
+int raduls_phase_times(double* host_ms, uint32_t count);
+/* Records handled by each stage of the last sort, waiting for the device:
+ * [2l] records in level l's buckets (histogram reads), [2l+1] records that
+ * level moved (scatter), l = 0..19; [40] records queued for the
+ * single-workgroup kernel, [41] records in tiny buckets, [42] records copied
+ * back from tmp.  `count` entries are written (43 cover all). */
+int raduls_last_work(uint64_t* host_out, uint32_t count);
 
 /* Bytes of library workspace a sort of n records needs (beyond the caller's
  * records and tmp). */

@@ -49,6 +49,7 @@ struct DeviceState {
   Work work{};
   uint64_t epochs_used = 0;
   uint64_t model_version = 0;
+  Plan last_plan{};
   hipEvent_t last_done = nullptr;
   hipStream_t last_stream = nullptr;
   hipStream_t capture_stream = nullptr;
@@ -59,6 +60,10 @@ struct DeviceState {
   uint32_t sample_period = 0;
   hipEvent_t t0 = nullptr, t1 = nullptr;
   bool timed = false;
+  // per-phase events of the last sort when phase timing is on
+  std::vector<hipEvent_t> ph_ev;
+  std::vector<int> ph_id;
+  bool ph_valid = false;
   int cu_count = 256;
 };
 
@@ -67,7 +72,7 @@ int g_sched_mode = RADULS_SCHED_HEURISTIC;
 int g_forced = 0;
 bool g_has_tuning = false;
 raduls_tuning g_tuning{};
-bool g_timing = false;
+int g_timing = 0;  // 0 off, 1 whole sort, 2 whole sort and phases
 bool g_model_loaded = false;
 std::vector<float> g_model_host;
 raduls_stats g_stats{};
@@ -331,18 +336,59 @@ raduls_tuning current_tuning(uint32_t r, uint32_t k, uint64_t n) {
   return g_has_tuning ? g_tuning : default_tuning(r, k, n);
 }
 
+// Phase ids for raduls_phase_times: 0 init+seed; for level l: 1+4l prepare
+// (tile ranges, histogram reset), 2+4l histogram, 3+4l scan, 4+4l scatter;
+// then PH_ORDER, PH_SMALL, PH_COPY.
+constexpr int PH_ORDER = 1 + 4 * (int)rd::LMAX, PH_SMALL = PH_ORDER + 1, PH_COPY = PH_ORDER + 2,
+              PH_COUNT = PH_ORDER + 3;
+
+struct PhaseMarks {
+  DeviceState* s;
+  hipStream_t st;
+  bool on;
+  int mark(int id) {
+    if (!on) return RADULS_OK;
+    size_t k = s->ph_id.size();
+    if (k >= s->ph_ev.size()) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreate(&e));
+      s->ph_ev.push_back(e);
+    }
+    s->ph_id.push_back(id);
+    HIPCHK(hipEventRecord(s->ph_ev[k], st));
+    return RADULS_OK;
+  }
+};
+
 // The launch sequence of one sort.  Every kernel reads its work from
 // device-side lists, so the sequence is the same for any data and can be
 // captured into a graph.
 void enqueue_sort(DeviceState& s, const Plan& p, void* records, void* tmp, const uint64_t* off, uint32_t S,
-                  hipStream_t st) {
+                  hipStream_t st, bool phases) {
+  PhaseMarks pm{&s, st, phases};
+  s.ph_id.clear();
+  pm.mark(-1);
   rd::launch_init(s.work, st);
   if (off) rd::launch_seed_segments(p, s.work, off, S, st);
   else rd::launch_seed_single(p, s.work, st);
-  for (uint32_t l = 0; l < p.lmax; l++) rd::launch_level(p, s.work, l, records, tmp, st);
+  pm.mark(0);
+  for (uint32_t l = 0; l < p.lmax; l++) {
+    rd::launch_level_prep(p, s.work, l, st);
+    pm.mark(1 + 4 * l);
+    rd::launch_level_hist(p, s.work, l, records, tmp, st);
+    pm.mark(2 + 4 * l);
+    rd::launch_level_scan(p, s.work, l, st);
+    pm.mark(3 + 4 * l);
+    rd::launch_level_scatter(p, s.work, l, records, tmp, st);
+    pm.mark(4 + 4 * l);
+  }
   rd::launch_order_small(p, s.work, st);
+  pm.mark(PH_ORDER);
   rd::launch_small(p, s.work, records, tmp, st);
+  pm.mark(PH_SMALL);
   rd::launch_copy(p, s.work, records, tmp, st);
+  pm.mark(PH_COPY);
+  s.ph_valid = phases;
 }
 
 int prepare(DeviceState& s, Plan& p, Layout& L, hipStream_t st) {
@@ -386,7 +432,8 @@ int raduls_sort(void* records, void* tmp, uint64_t n, uint32_t rec_bytes, uint32
     if (!s.t0) { HIPCHK(hipEventCreate(&s.t0)); HIPCHK(hipEventCreate(&s.t1)); }
     HIPCHK(hipEventRecord(s.t0, st));
   }
-  enqueue_sort(s, p, records, tmp, nullptr, 0, st);
+  enqueue_sort(s, p, records, tmp, nullptr, 0, st, g_timing >= 2);
+  s.last_plan = p;
   HIPCHK(hipGetLastError());
   if (g_timing) { HIPCHK(hipEventRecord(s.t1, st)); s.timed = true; }
   s.epochs_used += rd::LMAX + 1;
@@ -427,7 +474,7 @@ int raduls_sort_segmented(void* records, void* tmp, const uint64_t* seg_offsets,
   } else {
     hipGraph_t g = nullptr;
     HIPCHK(hipStreamBeginCapture(s.capture_stream, hipStreamCaptureModeThreadLocal));
-    enqueue_sort(s, p, records, tmp, seg_offsets, num_segs, s.capture_stream);
+    enqueue_sort(s, p, records, tmp, seg_offsets, num_segs, s.capture_stream, false);
     hipError_t e = hipStreamEndCapture(s.capture_stream, &g);
     if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
     e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
@@ -440,6 +487,7 @@ int raduls_sort_segmented(void* records, void* tmp, const uint64_t* seg_offsets,
     HIPCHK(hipEventRecord(s.t0, st));
   }
   HIPCHK(hipGraphLaunch(exec, st));
+  s.last_plan = p;
   if (g_timing) { HIPCHK(hipEventRecord(s.t1, st)); s.timed = true; }
   s.epochs_used += rd::LMAX + 1;
   g_stats.last_records = total_records;
@@ -480,11 +528,59 @@ int raduls_partition(const void* in, void* out, uint64_t n, uint32_t rec_bytes, 
   p.partition_bit = 8 * key_bytes - shift - bits;
   rd::launch_init(s.work, st);
   rd::launch_seed_single(p, s.work, st);
-  rd::launch_level(p, s.work, 0, const_cast<void*>(in), out, st);
+  rd::launch_level_prep(p, s.work, 0, st);
+  rd::launch_level_hist(p, s.work, 0, const_cast<void*>(in), out, st);
+  rd::launch_level_scan(p, s.work, 0, st);
+  rd::launch_level_scatter(p, s.work, 0, const_cast<void*>(in), out, st);
   HIPCHK(hipGetLastError());
   s.work.counts_out = nullptr;
   s.epochs_used += rd::LMAX + 1;
   return mark_done(s, st);
+}
+
+int raduls_last_work(uint64_t* host_out, uint32_t count) {
+  if (!host_out) return fail(RADULS_EINVAL, "null pointer");
+  std::lock_guard<std::mutex> lock(g_mu);
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  for (uint32_t i = 0; i < count; i++) host_out[i] = 0;
+  auto it = g_dev.find(dev);
+  if (it == g_dev.end() || !it->second.base) return RADULS_OK;
+  DeviceState& s = it->second;
+  HIPCHK(hipDeviceSynchronize());
+  rd::Ctl c;
+  HIPCHK(hipMemcpy(&c, s.work.ctl, sizeof(c), hipMemcpyDeviceToHost));
+  const Plan& p = s.last_plan;
+  auto put = [&](uint32_t i, uint64_t v) { if (i < count) host_out[i] = v; };
+  std::vector<rd::Bucket> v;
+  for (uint32_t l = 0; l < p.lmax && l < rd::LMAX; l++) {
+    uint64_t nb = std::min<uint64_t>(c.nbig[l], p.cap_big);
+    v.resize(nb);
+    if (nb) HIPCHK(hipMemcpy(v.data(), s.work.big + (uint64_t)l * p.cap_big, nb * sizeof(rd::Bucket), hipMemcpyDeviceToHost));
+    uint64_t all = 0, moved = 0;
+    for (auto& b : v) { all += b.count; if (!(b.flags & rd::BF_SKIP)) moved += b.count; }
+    put(2 * l, all);
+    put(2 * l + 1, moved);
+  }
+  uint64_t ns = std::min<uint64_t>(c.nsmall, p.cap_small);
+  v.resize(ns);
+  if (ns) HIPCHK(hipMemcpy(v.data(), s.work.small, ns * sizeof(rd::Bucket), hipMemcpyDeviceToHost));
+  uint64_t sm = 0;
+  for (auto& b : v) sm += b.count;
+  put(2 * rd::LMAX, sm);
+  uint64_t nt = std::min<uint64_t>(c.ntiny, p.cap_tiny);
+  std::vector<uint64_t> t(nt);
+  if (nt) HIPCHK(hipMemcpy(t.data(), s.work.tiny, nt * 8, hipMemcpyDeviceToHost));
+  uint64_t tr = 0;
+  for (uint64_t x : t) tr += (x >> 40) & 63u;
+  put(2 * rd::LMAX + 1, tr);
+  uint64_t nc = std::min<uint64_t>(c.ncopy, p.cap_copy);
+  v.resize(nc);
+  if (nc) HIPCHK(hipMemcpy(v.data(), s.work.copy, nc * sizeof(rd::Bucket), hipMemcpyDeviceToHost));
+  uint64_t cr = 0;
+  for (auto& b : v) cr += b.count;
+  put(2 * rd::LMAX + 2, cr);
+  return RADULS_OK;
 }
 
 int raduls_sync_check(void* stream) {
@@ -618,8 +714,29 @@ int raduls_trace_count(uint64_t* host_count, void* stream) {
 }
 
 int raduls_set_timing(int on) {
+  if (on < 0 || on > 2) return fail(RADULS_EINVAL, "timing mode must be 0, 1 or 2");
   std::lock_guard<std::mutex> lock(g_mu);
-  g_timing = on != 0;
+  g_timing = on;
+  return RADULS_OK;
+}
+
+int raduls_phase_times(double* host_ms, uint32_t count) {
+  if (!host_ms) return fail(RADULS_EINVAL, "null pointer");
+  std::lock_guard<std::mutex> lock(g_mu);
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  for (uint32_t i = 0; i < count; i++) host_ms[i] = 0.0;
+  auto it = g_dev.find(dev);
+  if (it == g_dev.end() || !it->second.ph_valid) return fail(RADULS_EINVAL, "no phase-timed sort recorded");
+  DeviceState& s = it->second;
+  if (s.ph_id.empty()) return RADULS_OK;
+  HIPCHK(hipEventSynchronize(s.ph_ev[s.ph_id.size() - 1]));
+  for (size_t k = 1; k < s.ph_id.size(); k++) {
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, s.ph_ev[k - 1], s.ph_ev[k]));
+    int id = s.ph_id[k];
+    if (id >= 0 && (uint32_t)id < count) host_ms[id] += ms;
+  }
   return RADULS_OK;
 }
 
@@ -693,6 +810,7 @@ void raduls_release(void) {
     if (s.last_done) hipEventDestroy(s.last_done);
     if (s.t0) hipEventDestroy(s.t0);
     if (s.t1) hipEventDestroy(s.t1);
+    for (hipEvent_t e : s.ph_ev) hipEventDestroy(e);
     if (s.capture_stream) hipStreamDestroy(s.capture_stream);
     (void)hipSetDevice(cur);
   }

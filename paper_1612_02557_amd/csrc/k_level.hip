@@ -523,21 +523,6 @@ __global__ void k_class_scatter(Plan p, Work w) {
 // ---------------------------------------------------------------------------
 // Host-side launchers.
 
-template <int RW>
-static void launch_level_rw(const Plan& p, const Work& w, uint32_t level, const uint8_t* rec0, uint8_t* rec0w,
-                            const uint8_t* rec1, uint8_t* rec1w, hipStream_t s) {
-  size_t stage = (size_t)p.tile * p.rec_bytes;
-  if (p.d_big <= 8) {
-    k_hist<RW, 8><<<p.grid_hist, WG, 0, s>>>(p, w, level, rec0, rec1);
-    k_scan<8><<<p.grid_clear, WG, 0, s>>>(p, w, level);
-    k_scatter<RW, 8><<<p.grid_scatter, WG, stage, s>>>(p, w, level, rec0, rec0w, rec1, rec1w);
-  } else {
-    k_hist<RW, 11><<<p.grid_hist, WG, 0, s>>>(p, w, level, rec0, rec1);
-    k_scan<11><<<p.grid_clear, WG, 0, s>>>(p, w, level);
-    k_scatter<RW, 11><<<p.grid_scatter, WG, stage, s>>>(p, w, level, rec0, rec0w, rec1, rec1w);
-  }
-}
-
 void launch_init(const Work& w, hipStream_t s) {
   k_init<<<1, WG, 0, s>>>(w);
 }
@@ -552,17 +537,42 @@ void launch_seed_segments(const Plan& p, const Work& w, const uint64_t* off, uin
   k_seed_segments<<<g, WG, 0, s>>>(p, w, off, S);
 }
 
-void launch_level(const Plan& p, const Work& w, uint32_t level, void* records, void* tmp, hipStream_t s) {
+void launch_level_prep(const Plan& p, const Work& w, uint32_t level, hipStream_t s) {
   k_prefix<<<1, WG, 0, s>>>(w.big + (uint64_t)level * p.cap_big, &w.ctl->nbig[level], p.cap_big,
                             w.tile_start + (uint64_t)level * (p.cap_big + 1), &w.ctl->ntiles[level],
                             &w.ctl->ticket[level], p.tile);
   k_clear_hist<<<p.grid_clear, WG, 0, s>>>(p, w, level);
+}
+
+void launch_level_hist(const Plan& p, const Work& w, uint32_t level, void* records, void* tmp, hipStream_t s) {
+  const uint8_t* r0 = (const uint8_t*)records;
+  const uint8_t* r1 = (const uint8_t*)tmp;
+  switch (p.rw * 2 + (p.d_big > 8 ? 1 : 0)) {
+#define RD_CASE(n)                                                                         \
+  case 2 * n: k_hist<n, 8><<<p.grid_hist, WG, 0, s>>>(p, w, level, r0, r1); break;       \
+  case 2 * n + 1: k_hist<n, 11><<<p.grid_hist, WG, 0, s>>>(p, w, level, r0, r1); break;
+    RD_CASE(1) RD_CASE(2) RD_CASE(3) RD_CASE(4) RD_CASE(5) RD_CASE(6) RD_CASE(7) RD_CASE(8)
+    RD_CASE(9) RD_CASE(10) RD_CASE(11) RD_CASE(12) RD_CASE(13) RD_CASE(14) RD_CASE(15) RD_CASE(16)
+#undef RD_CASE
+    default: break;
+  }
+}
+
+void launch_level_scan(const Plan& p, const Work& w, uint32_t level, hipStream_t s) {
+  if (p.d_big > 8) k_scan<11><<<p.grid_clear, WG, 0, s>>>(p, w, level);
+  else k_scan<8><<<p.grid_clear, WG, 0, s>>>(p, w, level);
+}
+
+void launch_level_scatter(const Plan& p, const Work& w, uint32_t level, void* records, void* tmp, hipStream_t s) {
   const uint8_t* r0 = (const uint8_t*)records;
   const uint8_t* r1 = (const uint8_t*)tmp;
   uint8_t* w0 = (uint8_t*)records;
   uint8_t* w1 = (uint8_t*)tmp;
-  switch (p.rw) {
-#define RD_CASE(n) case n: launch_level_rw<n>(p, w, level, r0, w0, r1, w1, s); break;
+  size_t stage = (size_t)p.tile * p.rec_bytes;
+  switch (p.rw * 2 + (p.d_big > 8 ? 1 : 0)) {
+#define RD_CASE(n)                                                                                              \
+  case 2 * n: k_scatter<n, 8><<<p.grid_scatter, WG, stage, s>>>(p, w, level, r0, w0, r1, w1); break;          \
+  case 2 * n + 1: k_scatter<n, 11><<<p.grid_scatter, WG, stage, s>>>(p, w, level, r0, w0, r1, w1); break;
     RD_CASE(1) RD_CASE(2) RD_CASE(3) RD_CASE(4) RD_CASE(5) RD_CASE(6) RD_CASE(7) RD_CASE(8)
     RD_CASE(9) RD_CASE(10) RD_CASE(11) RD_CASE(12) RD_CASE(13) RD_CASE(14) RD_CASE(15) RD_CASE(16)
 #undef RD_CASE

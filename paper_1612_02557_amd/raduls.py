@@ -84,6 +84,8 @@ _SIGS = {
     "raduls_trace_count": (_i32, [ctypes.POINTER(_u64), _vp]),
     "raduls_get_stats": (_i32, [ctypes.POINTER(Stats)]),
     "raduls_set_timing": (_i32, [_i32]),
+    "raduls_phase_times": (_i32, [ctypes.POINTER(ctypes.c_double), _u32]),
+    "raduls_last_work": (_i32, [ctypes.POINTER(_u64), _u32]),
     "raduls_workspace_bytes": (ctypes.c_size_t, [_u64, _u32, _u32]),
     "raduls_status_string": (ctypes.c_char_p, [_i32]),
     "raduls_last_error_message": (ctypes.c_char_p, []),
@@ -271,8 +273,36 @@ def get_stats() -> Stats:
     return s
 
 
-def set_timing(on: bool):
-    _check(lib().raduls_set_timing(1 if on else 0))
+def set_timing(mode):
+    """0 off, 1 whole sort (Stats.last_ms), 2 whole sort and per-phase times."""
+    _check(lib().raduls_set_timing(int(mode)))
+
+
+PHASES = 84
+
+
+def phase_names(lmax: int = 20):
+    names = ["setup"]
+    for l in range(20):
+        names += [f"L{l}.prep", f"L{l}.hist", f"L{l}.scan", f"L{l}.scatter"]
+    return names + ["order_small", "small", "copy"]
+
+
+def phase_times():
+    """{phase name: ms} of the last sort run with timing mode 2 (zero phases dropped)."""
+    arr = (ctypes.c_double * PHASES)()
+    _check(lib().raduls_phase_times(arr, PHASES))
+    return {n: arr[i] for i, n in enumerate(phase_names()) if arr[i] > 0}
+
+
+def last_work():
+    """Records handled per stage by the last sort: {'levels': [(in, moved), ...], 'small', 'tiny', 'copy'}."""
+    arr = (_u64 * 43)()
+    _check(lib().raduls_last_work(arr, 43))
+    levels = [(arr[2 * l], arr[2 * l + 1]) for l in range(20)]
+    while levels and levels[-1] == (0, 0):
+        levels.pop()
+    return {"levels": levels, "small": arr[40], "tiny": arr[41], "copy": arr[42]}
 
 
 def workspace_bytes(n: int, rec_bytes: int, key_bytes: int) -> int:
