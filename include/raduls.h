@@ -77,7 +77,7 @@ typedef struct raduls_tuning {
   uint32_t block_digit_bits;  /* digit width of one-workgroup radix passes, 1..11 */
   uint32_t tile_records;      /* records per tile of a multi-workgroup pass, 256..8192, power of 2 */
   uint32_t lds_finish_max;    /* largest bucket finished inside LDS (0 = as large as LDS allows) */
-  uint32_t bitonic_max;       /* largest bucket the bitonic finish accepts, power of 2 */
+  uint32_t bitonic_max;       /* largest bucket the bitonic finish accepts (0 = the LDS capacity) */
   uint32_t workgroups_per_cu; /* resident workgroups per CU assumed by the big threshold, 1..8 */
   uint64_t big_min;           /* big buckets hold more than max(2N/(3W), big_min) records */
   uint32_t nontemporal;       /* 1: non-temporal stores for scattered output */

@@ -136,7 +136,6 @@ int validate_tuning(const raduls_tuning& t) {
   if (t.block_digit_bits < 1 || t.block_digit_bits > 8) return fail(RADULS_EINVAL, "block_digit_bits must be 1..8");
   if (t.tile_records < 256 || t.tile_records > 8192 || (t.tile_records & (t.tile_records - 1)))
     return fail(RADULS_EINVAL, "tile_records must be a power of two in 256..8192");
-  if (t.bitonic_max && (t.bitonic_max & (t.bitonic_max - 1))) return fail(RADULS_EINVAL, "bitonic_max must be a power of two");
   if (t.workgroups_per_cu < 1 || t.workgroups_per_cu > 8) return fail(RADULS_EINVAL, "workgroups_per_cu must be 1..8");
   return RADULS_OK;
 }
@@ -156,24 +155,19 @@ Plan make_plan(uint64_t n, uint32_t r, uint32_t k, const raduls_tuning& t, int c
   uint32_t stage_budget = p.d_big > 8 ? 32768 : 65536;
   while (tile > 256 && (uint64_t)tile * r > stage_budget) tile /= 2;
   p.tile = tile;
-  // single-workgroup kernel: LDS finishing capacity, bitonic capacity,
-  // wavefront capacity and radix-pass tile, within the dynamic LDS budget
+  // single-workgroup kernel: LDS finishing capacity C (records staged plus
+  // two 64-bit composites each) and radix-pass tile, within its dynamic LDS
   const uint32_t dyn = 60 * 1024;
-  uint32_t cfin = 4096;
-  while (cfin > 256 && (uint64_t)cfin * r + std::max<uint64_t>(4ull * cfin, 16ull * std::min<uint32_t>(cfin, 1024)) > dyn)
-    cfin /= 2;
-  if (t.lds_finish_max) cfin = std::min<uint32_t>(cfin, std::max<uint32_t>(256, pow2_floor(t.lds_finish_max)));
+  uint32_t cfin = std::min<uint32_t>(4096, (dyn / (r + 16)) / 64 * 64);
+  if (t.lds_finish_max) cfin = std::min<uint32_t>(cfin, std::max<uint32_t>(64, t.lds_finish_max / 64 * 64));
   p.c_fin = cfin;
-  uint32_t bmax = std::min<uint32_t>(cfin, 1024);
-  while ((uint64_t)cfin * r + 16ull * bmax > dyn && bmax > 64) bmax /= 2;
-  if (t.bitonic_max) bmax = std::min(bmax, t.bitonic_max);
-  p.bitonic_max = bmax;
-  uint32_t ws = 256;
-  while (ws > 64 && 4ull * (ws * r + 16ull * ws + 1024) > dyn) ws -= 64;
-  p.wave_cap = ws;
-  uint32_t bt = pow2_floor(256 * ipt);
+  p.bitonic_max = t.bitonic_max ? std::min<uint32_t>(t.bitonic_max, cfin) : cfin;
+  uint32_t bt = 256 * std::min<uint32_t>(8, ipt);
   while (bt > 256 && (uint64_t)bt * r > dyn) bt /= 2;
-  p.block_tile = std::min<uint32_t>(bt, 4096);
+  p.block_tile = bt;
+  // wavefront jobs: four wave regions of records + 16 bytes of composites
+  // per record + 256 counters each
+  p.wave_cap = std::min<uint32_t>(256, ((dyn / 4 - 1024) / (r + 16)) / 64 * 64);
   p.nontemporal = t.nontemporal;
   p.grid_small = cus * t.workgroups_per_cu;
   p.grid_scatter = cus * 2;
@@ -189,6 +183,7 @@ Plan make_plan(uint64_t n, uint32_t r, uint32_t k, const raduls_tuning& t, int c
   p.cap_small = std::min<uint64_t>(n / 33 + 1, child_bound) + 1;
   p.cap_tiny = std::min<uint64_t>(n + 1, child_bound) + 1;
   p.cap_copy = std::min<uint64_t>(n / 64 + 1, child_bound) + 1;
+  p.cap_wg = p.cap_small + n / p.wave_cap + 2;
   p.max_tiles = n / p.tile + p.cap_big + 2;
   p.stack_cap = (uint32_t)std::min<uint64_t>(p.t_big / (p.c_fin + 1) + 4, 1u << 20);
   p.sched_mode = g_sched_mode;
@@ -200,7 +195,7 @@ Plan make_plan(uint64_t n, uint32_t r, uint32_t k, const raduls_tuning& t, int c
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t ctl, big, tile_start, hist, vary, small, small_ord, tiny, copy, copy_start, stacks, trace_count, total;
+  size_t ctl, big, tile_start, hist, vary, small, small_ord, tiny, copy, copy_start, stacks, wgjobs, trace_count, total;
   size_t status_total;  // epoch counter (256 bytes) + look-back words
 };
 
@@ -220,6 +215,7 @@ Layout layout_of(const Plan& p) {
   L.copy = take((size_t)p.cap_copy * sizeof(rd::Bucket));
   L.copy_start = take((size_t)(p.cap_copy + 1) * 8);
   L.stacks = take((size_t)p.grid_small * p.stack_cap * sizeof(rd::Bucket));
+  L.wgjobs = take((size_t)p.cap_wg * sizeof(rd::Bucket));
   L.trace_count = take(8);
   L.total = o;
   L.status_total = 256 + align_up((size_t)p.max_tiles * R * 8);
@@ -301,6 +297,7 @@ int ensure_workspace(DeviceState& s, const Plan& p, Layout& L, hipStream_t strea
   w.copy = (rd::Bucket*)(s.base + L.copy);
   w.copy_start = (uint64_t*)(s.base + L.copy_start);
   w.stacks = (rd::Bucket*)(s.base + L.stacks);
+  w.wgjobs = (rd::Bucket*)(s.base + L.wgjobs);
   w.model = g_model_loaded ? s.model : nullptr;
   w.trace = s.trace;
   w.trace_count = (uint64_t*)(s.base + L.trace_count);

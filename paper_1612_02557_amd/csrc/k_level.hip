@@ -16,7 +16,7 @@
 
 namespace rd {
 
-constexpr uint32_t LB_SPIN_LIMIT = 1u << 24;  // look-back waits this many polls at most
+constexpr uint32_t LB_SPIN_LIMIT = 1u << 16;  // look-back waits this many polls at most
 
 __device__ __forceinline__ Bucket* level_list(const Plan& p, const Work& w, uint32_t level) {
   return w.big + (uint64_t)level * p.cap_big;
@@ -239,7 +239,7 @@ __global__ __launch_bounds__(WG) void k_scan(Plan p, Work w, uint32_t level) {
   const uint32_t RS = 1u << p.d_big;
   for (uint32_t b = blockIdx.x; b < nb; b += gridDim.x) {
     Bucket B = list[b];
-    Key vary{w.vary[2 * b], w.vary[2 * b + 1]};
+    Key vary = Key{w.vary[2 * b], w.vary[2 * b + 1]};
     uint32_t d = min(p.d_big, kf.kbits - B.bit);
     if (p.partition) {
       // one stable pass for the caller: always move, report the counts
@@ -389,21 +389,20 @@ __global__ __launch_bounds__(WG) void k_scatter(Plan p, Work w, uint32_t level, 
         if (i < bend) rec[j] = load_rec<RW>(src, i);
       }
     }
+    RankPart rp[IPT_MAX];
 #pragma unroll
     for (uint32_t j = 0; j < IPT_MAX; j++) {
       if (j < IPT) {
         uint64_t i = wbase + (uint64_t)j * 64 + lane;
         bool valid = i < bend;
         uint32_t v = valid ? key_digit(rec_key<RW>(rec[j], kf), shift, mask) : 0u;
-        uint64_t active = __ballot(valid);
-        uint64_t peers = match_digit(v, d, active);
-        uint32_t before = (uint32_t)__popcll(peers & lanemask_lt());
-        uint32_t basec = valid ? wcnt[wave * RMAX + v] : 0u;
+        rp[j] = rank_issue(&wcnt[wave * RMAX], v, d, valid);
         dg[j] = v;
-        rk[j] = basec + before;
-        if (valid && before == 0) wcnt[wave * RMAX + v] = basec + (uint32_t)__popcll(peers);
       }
     }
+#pragma unroll
+    for (uint32_t j = 0; j < IPT_MAX; j++)
+      if (j < IPT) rk[j] = rank_finish(rp[j]);
     __syncthreads();
     for (uint32_t v = threadIdx.x; v < R; v += WG) {
       uint32_t s = 0;

@@ -3,13 +3,16 @@
 // processed by one thread) and the finishing sorts of Sec. 3.5.
 //
 // A persistent grid takes buckets from the queue, largest size class first.
-// A bucket larger than the LDS finishing capacity gets a one-workgroup radix
-// pass (RADIX); its children are routed: at most 32 records -> one wavefront
-// ranks them (RANK, the insertion-sort slot of Sec. 3.5); up to the LDS
-// capacity -> the scheduler picks LSD, BITONIC or (one more) RADIX; larger ->
-// the workgroup's own depth-first stack.  Small finishes run per wavefront
-// (four at a time), larger ones use the whole workgroup.  Every procedure is
-// stable, so the output does not depend on which one runs.
+// A bucket larger than the LDS finishing capacity C gets a one-workgroup
+// radix pass (RADIX).  Its children lie consecutively in digit order, so runs
+// of whole children holding at most C records are finished together: one
+// coalesced load into LDS, a stable sort there (LSD counting passes or a
+// bitonic network, as the scheduler picks), one coalesced store.  Children
+// above C go to the workgroup's own depth-first stack.  A queued bucket of at
+// most C records is finished directly (or, if the scheduler says so, split
+// once more first); one of at most 32 records is ranked by one wavefront
+// (RANK, the insertion-sort slot of Sec. 3.5).  Every procedure is stable, so
+// the output does not depend on which one runs.
 #include "raduls_dev.hpp"
 #include "raduls_kernels.hpp"
 #include "sched_dev.hpp"
@@ -18,12 +21,8 @@ namespace rd {
 
 constexpr uint32_t RB = 256;          // radix of one-workgroup passes (d_block <= 8)
 constexpr uint32_t MAX_ROUNDS = 16;   // LDS finishing capacity <= 16 * WG records
-constexpr uint32_t WAVE_MAX = 256;    // largest bucket a wavefront finishes
-constexpr uint32_t EMAX = WAVE_MAX / 64;
-
-// child codes
-constexpr uint32_t C_NONE = 0, C_WRANK = 1, C_WLSD = 2, C_WBIT = 3, C_GLSD = 4, C_GBIT = 5,
-                   C_GRADIX = 6, C_PUSH = 7, C_GCOPY = 8, C_CF = 9;
+constexpr uint32_t IPT_BLOCK = 8;     // records per thread in a radix-pass tile
+constexpr uint32_t EMAX = 4;          // records per lane of a wavefront job (at most 256)
 
 struct SmallShared {
   uint32_t hist[RB];
@@ -33,18 +32,18 @@ struct SmallShared {
   uint32_t tcnt[RB];
   uint32_t scan_tmp[NWAVES + 1];
   uint64_t vary[2 * NWAVES];
-  // child lists of up to two nested radix passes
-  uint32_t cbase[2][RB];
-  uint32_t ccnt[2][RB];
-  uint32_t ccode[2][RB];
-  uint32_t wlist[2][RB];
-  uint32_t glist[2][RB];
-  uint32_t wn[2], gn[2], wnext[2];
-  uint32_t cbit[2];
-  uint32_t cR[2];
-  uint32_t ctmp[2];
-  uint64_t cbegin[2];
-  uint64_t cparent[2];
+  // children of the current radix pass, grouped into finishing jobs
+  uint32_t cbase[RB + 1];  // child starts; then job starts and the end of the last job
+  uint32_t ccnt[RB];
+  uint32_t jb[RB];        // job start (offset in the parent bucket)
+  uint32_t jn[RB];        // job length
+  uint32_t jinfo[RB];     // shared key bits | procedure << 16 | sampled << 24 | feasible << 28
+  uint16_t glist[RB];     // workgroup jobs
+  uint32_t gjb[RB], gjn[RB];
+  uint8_t gbit[RB];
+  uint32_t nw, ng, wnext;
+  uint32_t cbit, pbit, cR, ctmp;
+  uint64_t cbegin, cparent;
   uint32_t sp;
   uint32_t bcast;
   uint32_t decisions;
@@ -60,7 +59,6 @@ struct Ctx {
   SmallShared* S;
   uint32_t* dyn;     // dynamic LDS
   Bucket* stack;
-  uint32_t ws;       // wavefront finishing capacity for this record size
 };
 
 __device__ __forceinline__ void wave_lds_sync() {
@@ -110,7 +108,7 @@ __device__ __forceinline__ Key mask128(Key k, uint32_t n) {
 
 // RANK: position = number of keys that are smaller, or equal and earlier.
 template <int RW>
-__device__ void wave_rank(Ctx& c, uint64_t begin, uint32_t m, bool in_tmp) {
+__device__ __forceinline__ void wave_rank(Ctx& c, uint64_t begin, uint32_t m, bool in_tmp) {
   const uint32_t l = lane_id();
   const uint8_t* src = in_tmp ? c.rec1 : c.rec0;
   Rec<RW> r;
@@ -131,17 +129,23 @@ struct Comp {
 };
 __device__ __forceinline__ bool comp_gt(Comp a, Comp b) { return a.hi > b.hi || (a.hi == b.hi && a.lo > b.lo); }
 
-// LSD or BITONIC on m <= 64*EMAX records by one wave.  Records are staged in
-// the wave's LDS region so the sorted order can be gathered from them.
+// LSD or BITONIC on m <= 64*EMAX records by one wave, no workgroup barrier.
+// The records are staged in the wave's own LDS region; the composites
+// (varying key bits << ib | local index) are sorted in registers -- bitonic
+// steps across lanes by shuffles and within a lane by register exchange --
+// or by stable counting passes through the wave's LDS, and the sorted
+// composites name the records to gather.
 template <int RW>
-__device__ void wave_sort(Ctx& c, uint64_t begin, uint32_t m, bool in_tmp, uint32_t proc, uint32_t* reg) {
+__device__ __forceinline__ void wave_sort(Ctx& c, uint64_t begin, uint32_t m, bool in_tmp, uint32_t proc,
+                                          uint32_t* reg) {
+  const uint32_t ws = c.p.wave_cap;
   const uint32_t l = lane_id();
   const uint8_t* src = in_tmp ? c.rec1 : c.rec0;
   const uint32_t E = (m + 63) / 64;
   uint32_t* recs = reg;                                             // ws * RW words
-  uint64_t* cl = reinterpret_cast<uint64_t*>(reg + c.ws * RW);      // ws comps (lo)
-  uint64_t* ch = cl + c.ws;                                         // ws comps (hi)
-  uint32_t* hist = reinterpret_cast<uint32_t*>(ch + c.ws);          // 256 counters
+  uint64_t* cl = reinterpret_cast<uint64_t*>(reg + ws * RW);      // ws comps (lo)
+  uint64_t* ch = cl + ws;                                         // ws comps (hi)
+  uint32_t* hist = reinterpret_cast<uint32_t*>(ch + ws);          // 256 counters
   Key key[EMAX];
 #pragma unroll
   for (uint32_t e = 0; e < EMAX; e++) {
@@ -160,7 +164,7 @@ __device__ void wave_sort(Ctx& c, uint64_t begin, uint32_t m, bool in_tmp, uint3
     uint32_t i = e * 64 + l;
     if (e < E && i < m) { vlo |= key[e].lo ^ ref.lo; vhi |= key[e].hi ^ ref.hi; }
   }
-  Key vary{wave_or64(vlo), wave_or64(vhi)};
+  Key vary = Key{wave_or64(vlo), wave_or64(vhi)};
   wave_lds_sync();
   if (vary.lo == 0 && vary.hi == 0) {
     // all keys equal: input order is the sorted order
@@ -230,22 +234,21 @@ __device__ void wave_sort(Ctx& c, uint64_t begin, uint32_t m, bool in_tmp, uint3
       for (uint32_t v = l; v < R; v += 64) hist[v] = 0;
       wave_lds_sync();
       uint32_t dg[EMAX], rk[EMAX];
+      RankPart rp[EMAX];
 #pragma unroll
       for (uint32_t e = 0; e < EMAX; e++) {
         if (e < E) {
           uint32_t i = e * 64 + l;
           bool valid = i < m;
           uint32_t v = (uint32_t)shr128(Key{cp[e].lo, cp[e].hi}, sh).lo & (R - 1);
-          uint64_t active = __ballot(valid);
-          uint64_t peers = match_digit(v, d, active);
-          uint32_t before = (uint32_t)__popcll(peers & lanemask_lt());
-          uint32_t base = valid ? hist[v] : 0u;
+          rp[e] = rank_issue(hist, v, d, valid);
           dg[e] = v;
-          rk[e] = base + before;
-          if (valid && before == 0) hist[v] = base + (uint32_t)__popcll(peers);
-          wave_lds_sync();
         }
       }
+#pragma unroll
+      for (uint32_t e = 0; e < EMAX; e++)
+        if (e < E) rk[e] = rank_finish(rp[e]);
+      wave_lds_sync();
       // exclusive scan of the R counters: each lane sums a run of 4
       uint32_t h[4], loc = 0;
 #pragma unroll
@@ -286,12 +289,13 @@ __device__ void wave_sort(Ctx& c, uint64_t begin, uint32_t m, bool in_tmp, uint3
   wave_lds_sync();
 }
 
+
 // ---------------------------------------------------------------------------
 // Workgroup procedures.
 
 // Load m records into the LDS stage and reduce the varying-bit mask.
 template <int RW>
-__device__ Key wg_stage(Ctx& c, uint64_t begin, uint32_t m, bool in_tmp) {
+__device__ __forceinline__ Key wg_stage(Ctx& c, uint64_t begin, uint32_t m, bool in_tmp) {
   const uint8_t* src = in_tmp ? c.rec1 : c.rec0;
   SmallShared& S = *c.S;
   for (uint32_t q0 = 0; q0 < m; q0 += WG * 8) {
@@ -328,8 +332,8 @@ __device__ Key wg_stage(Ctx& c, uint64_t begin, uint32_t m, bool in_tmp) {
 
 // Per-digit wave offsets and tile offsets after ranking: wcnt[q][v] becomes
 // the count of digit v in waves before q, tcnt[v] the tile count, toff[v]
-// the first LDS slot of digit v.
-__device__ void tile_offsets(SmallShared& S, uint32_t R) {
+// the first slot of digit v.
+__device__ __forceinline__ void tile_offsets(SmallShared& S, uint32_t R) {
   __syncthreads();
   for (uint32_t v = threadIdx.x; v < R; v += WG) {
     uint32_t s = 0;
@@ -342,52 +346,183 @@ __device__ void tile_offsets(SmallShared& S, uint32_t R) {
   block_excl_scan_lds(S.toff, R, S.scan_tmp);
 }
 
-__device__ __forceinline__ uint32_t rank_digit(uint32_t* wc, uint32_t v, uint32_t d, bool valid) {
-  uint64_t active = __ballot(valid);
-  uint64_t peers = match_digit(v, d, active);
-  uint32_t before = (uint32_t)__popcll(peers & lanemask_lt());
-  uint32_t base = valid ? wc[v] : 0u;
-  if (valid && before == 0) wc[v] = base + (uint32_t)__popcll(peers);
-  return base + before;
+// One stable counting pass over 64-bit values in LDS (digit = bits
+// [shift, shift + d) of the value): src -> dst.  Wave q owns positions
+// [q*PW, (q+1)*PW), taken 64 at a time, so ranks follow position order.
+__device__ __forceinline__ void lds_pass64(SmallShared& S, const uint64_t* src, uint64_t* dst, uint32_t m, uint32_t shift,
+                           uint32_t d) {
+  const uint32_t wave = threadIdx.x / 64, lane = lane_id();
+  const uint32_t R = 1u << d;
+  const uint32_t PW = ((m + NWAVES * 64 - 1) / (NWAVES * 64)) * 64;
+  const uint32_t NR = PW / 64;
+  for (uint32_t i = threadIdx.x; i < NWAVES * RB; i += WG) S.wcnt[i] = 0;
+  __syncthreads();
+  uint64_t xv[MAX_ROUNDS];
+  uint32_t dg[MAX_ROUNDS], rk[MAX_ROUNDS];
+  RankPart rp[MAX_ROUNDS];
+#pragma unroll
+  for (uint32_t j = 0; j < MAX_ROUNDS; j++) {
+    if (j < NR) {
+      uint32_t q = wave * PW + j * 64 + lane;
+      bool valid = q < m;
+      uint64_t x = valid ? src[q] : 0ull;
+      uint32_t v = (uint32_t)(x >> shift) & (R - 1);
+      rp[j] = rank_issue(&S.wcnt[wave * RB], v, d, valid);
+      dg[j] = v;
+      xv[j] = x;
+    }
+  }
+#pragma unroll
+  for (uint32_t j = 0; j < MAX_ROUNDS; j++)
+    if (j < NR) rk[j] = rank_finish(rp[j]);
+  tile_offsets(S, R);
+#pragma unroll
+  for (uint32_t j = 0; j < MAX_ROUNDS; j++) {
+    if (j < NR) {
+      uint32_t q = wave * PW + j * 64 + lane;
+      if (q < m) dst[S.toff[dg[j]] + S.wcnt[wave * RB + dg[j]] + rk[j]] = xv[j];
+    }
+  }
+  __syncthreads();
 }
 
-// LSD inside LDS: a permutation of local indices is refined by stable
-// counting passes over the varying key bits, least significant first.
+// Finish m <= C records at [begin, begin+m) of one buffer into records,
+// stably by key.  The records are staged in LDS; what is sorted is the
+// composite (key bits that vary in this range) << ib | local index, so the
+// sort needs no tie rule and its result names the record to gather.
+//   LSD     stable counting passes over the varying bits, 8 at a time,
+//           least significant first (paper, Sec. 1)
+//   BITONIC a bitonic network on the (unique) composites
+// When the varying bits and the index do not fit in 64 bits, LSD refines a
+// permutation reading the keys from the stage, and BITONIC sorts 128-bit
+// composites.
 template <int RW>
-__device__ void wg_lsd(Ctx& c, uint64_t begin, uint32_t m, bool in_tmp) {
+__device__ __forceinline__ void wg_finish(Ctx& c, uint64_t begin, uint32_t m, bool in_tmp, uint32_t proc) {
   SmallShared& S = *c.S;
-  Key vary = wg_stage<RW>(c, begin, m, in_tmp);
-  uint16_t* perm0 = reinterpret_cast<uint16_t*>(c.dyn + c.p.c_fin * RW);
-  uint16_t* perm1 = perm0 + c.p.c_fin;
-  const uint32_t wave = threadIdx.x / 64, lane = lane_id();
-  if (vary.lo == 0 && vary.hi == 0) {
-    if (in_tmp)
-      for (uint32_t q = threadIdx.x; q < m; q += WG) store_rec<RW>(c.rec0, begin + q, lds_get<RW>(c.dyn, q), false);
+  if (m <= 1) {
+    if (m == 1 && in_tmp && threadIdx.x == 0) store_rec<RW>(c.rec0, begin, load_rec<RW>(c.rec1, begin), false);
     __syncthreads();
     return;
   }
-  const uint32_t lo = ctz128(vary), hi = bitlen128(vary);
+  const uint32_t C = c.p.c_fin;
+  Key vary = wg_stage<RW>(c, begin, m, in_tmp);
+  const uint32_t* stage = c.dyn;
+  if (vary.lo == 0 && vary.hi == 0) {
+    if (in_tmp)
+      for (uint32_t q = threadIdx.x; q < m; q += WG) store_rec<RW>(c.rec0, begin + q, lds_get<RW>(stage, q), false);
+    __syncthreads();
+    return;
+  }
+  const uint32_t lo = ctz128(vary);
+  const uint32_t W = bitlen128(vary) - lo;
+  const uint32_t ib = 32 - __clz(m - 1);
+  uint64_t* c0 = reinterpret_cast<uint64_t*>(c.dyn + C * RW);
+  uint64_t* c1 = c0 + C;
+  uint32_t P = 1;
+  while (P < m) P <<= 1;
+  const uint64_t imask = (1ull << ib) - 1;
+  if (W + ib <= 64) {
+    const uint32_t n_fill = proc == P_BITONIC ? P : m;
+    for (uint32_t q = threadIdx.x; q < n_fill; q += WG) {
+      if (q < m) {
+        Key k = lds_key<RW>(stage, q, c.kf);
+        uint64_t v = shr128(k, lo).lo & (W >= 64 ? ~0ull : ((1ull << W) - 1));
+        c0[q] = (v << ib) | q;
+      } else {
+        c0[q] = ~0ull;
+      }
+    }
+    __syncthreads();
+    const uint64_t* out = c0;
+    if (proc == P_BITONIC) {
+      for (uint32_t k = 2; k <= P; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+          for (uint32_t t = threadIdx.x; t < P / 2; t += WG) {
+            uint32_t a = 2 * j * (t / j) + (t % j);
+            uint32_t b = a + j;
+            bool asc = (a & k) == 0;
+            uint64_t x = c0[a], y = c0[b];
+            if ((x > y) == asc) { c0[a] = y; c0[b] = x; }
+          }
+          __syncthreads();
+        }
+      }
+    } else {
+      uint64_t* a = c0;
+      uint64_t* b = c1;
+      for (uint32_t s = 0; s < W; s += 8) {
+        lds_pass64(S, a, b, m, ib + s, min(8u, W - s));
+        uint64_t* t = a; a = b; b = t;
+      }
+      out = a;
+    }
+    for (uint32_t q = threadIdx.x; q < m; q += WG)
+      store_rec<RW>(c.rec0, begin + q, lds_get<RW>(stage, (uint32_t)(out[q] & imask)), false);
+    __syncthreads();
+    return;
+  }
+  if (proc == P_BITONIC && P <= C) {
+    uint64_t* cl = c0;
+    uint64_t* ch = c0 + P;
+    for (uint32_t q = threadIdx.x; q < P; q += WG) {
+      if (q < m) {
+        Key v = shl128(mask128(shr128(lds_key<RW>(stage, q, c.kf), lo), W), ib);
+        cl[q] = v.lo | q;
+        ch[q] = v.hi;
+      } else {
+        cl[q] = ~0ull;
+        ch[q] = ~0ull;
+      }
+    }
+    __syncthreads();
+    for (uint32_t k = 2; k <= P; k <<= 1) {
+      for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+        for (uint32_t t = threadIdx.x; t < P / 2; t += WG) {
+          uint32_t a = 2 * j * (t / j) + (t % j);
+          uint32_t b = a + j;
+          bool asc = (a & k) == 0;
+          uint64_t xl = cl[a], xh = ch[a], yl = cl[b], yh = ch[b];
+          bool gt = xh > yh || (xh == yh && xl > yl);
+          if (gt == asc) { cl[a] = yl; ch[a] = yh; cl[b] = xl; ch[b] = xh; }
+        }
+        __syncthreads();
+      }
+    }
+    for (uint32_t q = threadIdx.x; q < m; q += WG)
+      store_rec<RW>(c.rec0, begin + q, lds_get<RW>(stage, (uint32_t)(cl[q] & imask)), false);
+    __syncthreads();
+    return;
+  }
+  // wide keys: refine a permutation of local indices
+  uint16_t* perm0 = reinterpret_cast<uint16_t*>(c0);
+  uint16_t* perm1 = perm0 + C;
+  const uint32_t wave = threadIdx.x / 64, lane = lane_id();
   for (uint32_t q = threadIdx.x; q < m; q += WG) perm0[q] = (uint16_t)q;
-  const uint32_t PW = ((m + NWAVES * 64 - 1) / (NWAVES * 64)) * 64;  // positions per wave
+  const uint32_t PW = ((m + NWAVES * 64 - 1) / (NWAVES * 64)) * 64;
   const uint32_t NR = PW / 64;
+  const uint32_t hi = lo + W;
   for (uint32_t s = lo; s < hi; s += 8) {
     const uint32_t d = min(8u, hi - s);
     const uint32_t R = 1u << d;
     for (uint32_t i = threadIdx.x; i < NWAVES * RB; i += WG) S.wcnt[i] = 0;
     __syncthreads();
     uint32_t dg[MAX_ROUNDS], rk[MAX_ROUNDS], ix[MAX_ROUNDS];
+    RankPart rp[MAX_ROUNDS];
 #pragma unroll
     for (uint32_t j = 0; j < MAX_ROUNDS; j++) {
       if (j < NR) {
         uint32_t q = wave * PW + j * 64 + lane;
         bool valid = q < m;
         uint32_t idx = valid ? perm0[q] : 0u;
-        uint32_t v = valid ? key_digit(lds_key<RW>(c.dyn, idx, c.kf), s, R - 1) : 0u;
-        rk[j] = rank_digit(&S.wcnt[wave * RB], v, d, valid);
+        uint32_t v = valid ? key_digit(lds_key<RW>(stage, idx, c.kf), s, R - 1) : 0u;
+        rp[j] = rank_issue(&S.wcnt[wave * RB], v, d, valid);
         dg[j] = v;
         ix[j] = idx;
       }
     }
+#pragma unroll
+    for (uint32_t j = 0; j < MAX_ROUNDS; j++)
+      if (j < NR) rk[j] = rank_finish(rp[j]);
     tile_offsets(S, R);
 #pragma unroll
     for (uint32_t j = 0; j < MAX_ROUNDS; j++) {
@@ -399,59 +534,13 @@ __device__ void wg_lsd(Ctx& c, uint64_t begin, uint32_t m, bool in_tmp) {
     __syncthreads();
     uint16_t* t = perm0; perm0 = perm1; perm1 = t;
   }
-  for (uint32_t q = threadIdx.x; q < m; q += WG) store_rec<RW>(c.rec0, begin + q, lds_get<RW>(c.dyn, perm0[q]), false);
-  __syncthreads();
-}
-
-// Bitonic sort of (varying key bits, local index) composites in LDS.
-template <int RW>
-__device__ void wg_bitonic(Ctx& c, uint64_t begin, uint32_t m, bool in_tmp) {
-  Key vary = wg_stage<RW>(c, begin, m, in_tmp);
-  if (vary.lo == 0 && vary.hi == 0) {
-    if (in_tmp)
-      for (uint32_t q = threadIdx.x; q < m; q += WG) store_rec<RW>(c.rec0, begin + q, lds_get<RW>(c.dyn, q), false);
-    __syncthreads();
-    return;
-  }
-  const uint32_t lo = ctz128(vary);
-  const uint32_t wv = bitlen128(vary) - lo;
-  const uint32_t ib = 32 - __clz(m - 1);
-  uint32_t P = 1;
-  while (P < m) P <<= 1;
-  uint64_t* cl = reinterpret_cast<uint64_t*>(c.dyn + c.p.c_fin * RW);
-  uint64_t* ch = cl + c.p.bitonic_max;
-  for (uint32_t q = threadIdx.x; q < P; q += WG) {
-    if (q < m) {
-      Key v = shl128(mask128(shr128(lds_key<RW>(c.dyn, q, c.kf), lo), wv), ib);
-      cl[q] = v.lo | q;
-      ch[q] = v.hi;
-    } else {
-      cl[q] = ~0ull;
-      ch[q] = ~0ull;
-    }
-  }
-  __syncthreads();
-  for (uint32_t k = 2; k <= P; k <<= 1) {
-    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-      for (uint32_t t = threadIdx.x; t < P / 2; t += WG) {
-        uint32_t a = 2 * j * (t / j) + (t % j);
-        uint32_t b = a + j;
-        bool asc = (a & k) == 0;
-        Comp x{cl[a], ch[a]}, y{cl[b], ch[b]};
-        if (comp_gt(x, y) == asc) { cl[a] = y.lo; ch[a] = y.hi; cl[b] = x.lo; ch[b] = x.hi; }
-      }
-      __syncthreads();
-    }
-  }
-  const uint64_t imask = (1ull << ib) - 1;
-  for (uint32_t q = threadIdx.x; q < m; q += WG)
-    store_rec<RW>(c.rec0, begin + q, lds_get<RW>(c.dyn, (uint32_t)(cl[q] & imask)), false);
+  for (uint32_t q = threadIdx.x; q < m; q += WG) store_rec<RW>(c.rec0, begin + q, lds_get<RW>(stage, perm0[q]), false);
   __syncthreads();
 }
 
 // Copy a finished bucket from tmp to records.
 template <int RW>
-__device__ void wg_copy(Ctx& c, uint64_t begin, uint64_t m) {
+__device__ __forceinline__ void wg_copy(Ctx& c, uint64_t begin, uint64_t m) {
   for (uint64_t q = threadIdx.x; q < m; q += WG) store_rec<RW>(c.rec0, begin + q, load_rec<RW>(c.rec1, begin + q), false);
 }
 
@@ -459,10 +548,10 @@ __device__ void wg_copy(Ctx& c, uint64_t begin, uint64_t m) {
 // Sec. 3.4).  Sweep 1 counts digits and finds the bits all keys share (they
 // are skipped); sweep 2 moves records tile by tile to the other buffer, each
 // tile ranked stably and staged in LDS, digit runs appended in tile order.
-// Fills child list `slot`.  Returns false if every key is equal (the bucket
-// is then already finished in records).
+// Fills the child list.  Returns false if every key is equal (the bucket is
+// then already finished in records).
 template <int RW>
-__device__ bool block_pass(Ctx& c, const Bucket& b, uint32_t slot) {
+__device__ __forceinline__ bool block_pass(Ctx& c, const Bucket& b) {
   SmallShared& S = *c.S;
   const uint32_t wave = threadIdx.x / 64, lane = lane_id();
   const bool in_tmp = b.flags & BF_TMP;
@@ -506,6 +595,7 @@ __device__ bool block_pass(Ctx& c, const Bucket& b, uint32_t slot) {
     Key vary{0, 0};
 #pragma unroll
     for (int q = 0; q < NWAVES; q++) { vary.lo |= S.vary[2 * q]; vary.hi |= S.vary[2 * q + 1]; }
+    vary = vary;
     __syncthreads();
     if (vary.lo == 0 && vary.hi == 0) {
       if (in_tmp) wg_copy<RW>(c, b.begin, m);
@@ -517,22 +607,24 @@ __device__ bool block_pass(Ctx& c, const Bucket& b, uint32_t slot) {
     break;
   }
   // digit offsets
-  for (uint32_t v = threadIdx.x; v < R; v += WG) { S.ccnt[slot][v] = S.hist[v]; S.toff[v] = S.hist[v]; }
+  for (uint32_t v = threadIdx.x; v < R; v += WG) { S.ccnt[v] = S.hist[v]; S.toff[v] = S.hist[v]; }
   __syncthreads();
   block_excl_scan_lds(S.toff, R, S.scan_tmp);
-  for (uint32_t v = threadIdx.x; v < R; v += WG) { S.cbase[slot][v] = S.toff[v]; S.run[v] = S.toff[v]; }
+  for (uint32_t v = threadIdx.x; v < R; v += WG) { S.cbase[v] = S.toff[v]; S.run[v] = S.toff[v]; }
   if (threadIdx.x == 0) {
-    S.cbit[slot] = bit + d;
-    S.ctmp[slot] = in_tmp ? 0u : 1u;
-    S.cbegin[slot] = b.begin;
-    S.cparent[slot] = m;
+    S.cbit = bit + d;
+    S.pbit = bit;
+    S.cR = R;
+    S.ctmp = in_tmp ? 0u : 1u;
+    S.cbegin = b.begin;
+    S.cparent = m;
   }
   __syncthreads();
   // sweep 2: stable tiles through LDS
   const uint32_t BT = c.p.block_tile;
   const uint32_t per_wave = BT / NWAVES;
   const uint32_t IPT = BT / WG;
-  constexpr uint32_t IPT_MAX = RW >= 2 ? 64 / RW : 32;
+  constexpr uint32_t IPT_MAX = (RW >= 2 ? 64 / RW : 32) < IPT_BLOCK ? (RW >= 2 ? 64 / RW : 32) : IPT_BLOCK;
   for (uint32_t t0 = 0; t0 < m; t0 += BT) {
     const uint32_t cnt = min(BT, m - t0);
     for (uint32_t i = threadIdx.x; i < NWAVES * RB; i += WG) S.wcnt[i] = 0;
@@ -545,16 +637,20 @@ __device__ bool block_pass(Ctx& c, const Bucket& b, uint32_t slot) {
       uint32_t q = wb + j * 64 + lane;
       if (j < IPT && q < m) rec[j] = load_rec<RW>(src, b.begin + q);
     }
+    RankPart rp[IPT_MAX];
 #pragma unroll
     for (uint32_t j = 0; j < IPT_MAX; j++) {
       if (j < IPT) {
         uint32_t q = wb + j * 64 + lane;
         bool valid = q < m;
         uint32_t v = valid ? key_digit(rec_key<RW>(rec[j], c.kf), shift, R - 1) : 0u;
-        rk[j] = rank_digit(&S.wcnt[wave * RB], v, d, valid);
+        rp[j] = rank_issue(&S.wcnt[wave * RB], v, d, valid);
         dg[j] = v;
       }
     }
+#pragma unroll
+    for (uint32_t j = 0; j < IPT_MAX; j++)
+      if (j < IPT) rk[j] = rank_finish(rp[j]);
     tile_offsets(S, R);
 #pragma unroll
     for (uint32_t j = 0; j < IPT_MAX; j++) {
@@ -571,14 +667,12 @@ __device__ bool block_pass(Ctx& c, const Bucket& b, uint32_t slot) {
     for (uint32_t v = threadIdx.x; v < R; v += WG) S.run[v] += S.tcnt[v];
     __syncthreads();
   }
-  if (threadIdx.x == 0) S.cR[slot] = R;  // number of digits, read by the caller
-  __syncthreads();
   return true;
 }
 
 // ---------------------------------------------------------------------------
-// Tracing: one row per scheduled bucket.
-__device__ void trace_row(Ctx& c, uint64_t m, uint64_t parent, uint32_t bit, uint32_t chosen, uint32_t observed,
+// Tracing: one row per scheduled job.
+__device__ __forceinline__ void trace_row(Ctx& c, uint64_t m, uint64_t parent, uint32_t bit, uint32_t chosen, uint32_t observed,
                           const uint32_t* ticks, uint32_t flags) {
   if (!c.w.trace) return;
   uint64_t i = atomicAdd((unsigned long long*)c.w.trace_count, 1ull);
@@ -594,204 +688,243 @@ __device__ void trace_row(Ctx& c, uint64_t m, uint64_t parent, uint32_t bit, uin
 }
 
 template <int RW, bool ALLOW_RADIX>
-__device__ void run_wg_proc(Ctx& c, uint32_t proc, uint64_t begin, uint32_t m, uint32_t bit, bool in_tmp,
-                            uint64_t parent);
+__device__ __forceinline__ void run_job(Ctx& c, uint32_t proc, uint64_t begin, uint32_t m, uint32_t bit, bool in_tmp,
+                                        uint64_t parent);
 
-// Route the children of a radix pass held in child list `slot`.  Children of
-// slot 0 may get one more radix pass (slot 1); children of slot 1 are all
-// finished directly, so the nesting ends there.
-template <int RW, uint32_t slot>
-__device__ void handle_children(Ctx& c) {
+// Is this job sampled for counterfactual timing?  (Workgroup-uniform.)
+__device__ __forceinline__ bool sample_job(Ctx& c, uint32_t feas) {
+  if (!c.w.trace || !c.p.sample_period || __popc(feas) < 2) return false;
   SmallShared& S = *c.S;
-  const uint32_t R = S.cR[slot];
-  const uint32_t KB = c.kf.kbits;
-  const uint32_t cb = S.cbit[slot];
-  const bool ctmp = S.ctmp[slot] != 0;
-  const uint64_t base = S.cbegin[slot];
-  const uint64_t parent = S.cparent[slot];
-  if (threadIdx.x == 0) { S.wn[slot] = 0; S.gn[slot] = 0; S.wnext[slot] = 0; }
   __syncthreads();
-  // classify: one child per thread (R <= WG)
-  for (uint32_t v = threadIdx.x; v < R; v += WG) {
-    uint32_t cnt = S.ccnt[slot][v];
-    uint32_t code = C_NONE;
-    if (cnt == 0) {
-    } else if (cnt == 1 || cb >= KB) {
-      if (ctmp) code = cnt <= 64 ? C_WRANK : C_GCOPY;
-    } else if (cnt <= TINY_MAX) {
-      code = C_WRANK;
-    } else if (cnt > c.p.c_fin) {
-      code = C_PUSH;
-    } else {
-      uint32_t feas = feasible_mask(c.p, cnt, cb, KB, slot == 0);
-      uint32_t proc = choose_proc(c.p, c.w.model, cnt, parent, cb, KB, feas);
-      bool sample = false;
+  if (threadIdx.x == 0) {
+    uint32_t k = S.decisions++;
+    S.bcast = ((k + blockIdx.x * 7919u) % c.p.sample_period) == 0 ? 1u : 0u;
+  }
+  __syncthreads();
+  bool s = S.bcast != 0;
+  __syncthreads();
+  return s;
+}
+
+// Schedule and run one workgroup job of m <= C records (a queued bucket or a
+// child), tracing it if asked.  In a counterfactual sample every feasible
+// procedure runs in turn on the same input (each is a complete stable sort,
+// so later runs see input that is already in order and rewrite the same
+// bytes) and the chosen one runs last.
+template <int RW, bool ALLOW_RADIX>
+__device__ __forceinline__ void schedule_job(Ctx& c, uint64_t begin, uint32_t m, uint32_t bit, bool in_tmp,
+                                             uint64_t parent) {
+  const uint32_t KB = c.kf.kbits;
+  const uint32_t feas = feasible_mask(c.p, m, bit, KB, ALLOW_RADIX);
+  const uint32_t proc = choose_proc(c.p, c.w.model, m, parent, bit, KB, feas);
+  const bool cf = sample_job(c, feas);
+  const uint32_t runs = cf ? 3u : 1u;
+  uint32_t ticks[3] = {0, 0, 0};
+#pragma unroll 1
+  for (uint32_t k = 1; k <= runs; k++) {
+    const uint32_t q = cf ? (proc + k) % 3 : proc;
+    if (!((feas >> q) & 1u) && cf) continue;
+    __syncthreads();
+    uint64_t t0 = now_ticks();
+    run_job<RW, ALLOW_RADIX>(c, q, begin, m, bit, in_tmp, parent);
+    __syncthreads();
+    ticks[q] = (uint32_t)(now_ticks() - t0);
+  }
+  if (c.w.trace && __popc(feas) > 1 && threadIdx.x == 0)
+    trace_row(c, m, parent, bit, proc, cf ? feas : (1u << proc), ticks, cf ? 1u : 0u);
+  __syncthreads();
+}
+
+// Group the children of the last radix pass into finishing jobs.  Children
+// lie consecutively in key order, so a run of whole children is a valid job:
+// sorting the run by key sorts each child and leaves the children in place.
+// With T = half the wavefront capacity, a child above T is a job of its own
+// and smaller children are grouped by the T-window their first record falls
+// in, so a group holds at most 2T records.  Jobs of at most the wavefront
+// capacity go to the wavefront list; larger ones (single children of at most
+// C records) to the workgroup list, or are deferred to the global list; a
+// child above C goes to the workgroup's stack.  All threads take part.
+template <int RW, bool DEFER>
+__device__ __forceinline__ void build_jobs(Ctx& c) {
+  SmallShared& S = *c.S;
+  const uint32_t C = c.p.c_fin;
+  const uint32_t WSC = c.p.wave_cap;
+  const uint32_t T = WSC / 2;
+  const uint32_t KB = c.kf.kbits;
+  const uint32_t R = S.cR;
+  const uint32_t t = threadIdx.x;
+  // 1. compact the non-empty children (stable)
+  const uint32_t cnt = t < R ? S.ccnt[t] : 0u;
+  const uint32_t st = t < R ? S.cbase[t] : 0u;
+  S.toff[t] = cnt > 0 ? 1u : 0u;
+  if (t == 0) { S.nw = 0; S.ng = 0; S.wnext = 0; }
+  __syncthreads();
+  const uint32_t nn = block_excl_scan_lds(S.toff, WG, S.scan_tmp);
+  if (cnt > 0) { S.jb[S.toff[t]] = st; S.jn[S.toff[t]] = cnt; }
+  __syncthreads();
+  // 2. job boundaries among the compacted children
+  uint32_t kst = 0, kcnt = 0, kbnd = 0;
+  if (t < nn) {
+    kst = S.jb[t];
+    kcnt = S.jn[t];
+    kbnd = 1;
+    if (t > 0) {
+      uint32_t pst = S.jb[t - 1], pcnt = S.jn[t - 1];
+      kbnd = (kcnt > T || pcnt > T || kst / T != pst / T) ? 1u : 0u;
+    }
+  }
+  __syncthreads();
+  S.toff[t] = kbnd;
+  __syncthreads();
+  const uint32_t nj = block_excl_scan_lds(S.toff, WG, S.scan_tmp);
+  // job j: start (cbase[j]) and size of its first child (ccnt[j]); cbase[nj]
+  // is the end of the last child
+  if (kbnd) { S.cbase[S.toff[t]] = kst; S.ccnt[S.toff[t]] = kcnt; }
+  if (t < nn && t + 1 == nn) S.cbase[nj] = kst + kcnt;
+  __syncthreads();
+  // 3. classify the jobs (one per thread) and choose their procedures
+  const uint32_t cb = S.cbit, pb = S.pbit;
+  const bool ctmp = S.ctmp != 0;
+  const uint64_t parent = S.cparent;
+  for (uint32_t j = t; j < nj; j += WG) {
+    const uint32_t js = S.cbase[j];
+    const uint32_t m = S.cbase[j + 1] - js;
+    const uint32_t bit = m == S.ccnt[j] ? cb : pb;
+    const uint32_t ib = 32 - __clz(m > 1 ? m - 1 : 1);
+    if (m > C) {
+      uint32_t sp = atomicAdd(&S.sp, 1u);
+      if (sp < c.p.stack_cap) c.stack[sp] = Bucket{S.cbegin + js, m, parent, cb, ctmp ? BF_TMP : 0u};
+      else atomicOr(&c.w.ctl->overflow, 16u);
+      continue;
+    }
+    if (m <= TINY_MAX || (m <= WSC && (KB - bit) + ib <= 128)) {
+      uint32_t feas = m > TINY_MAX ? feasible_mask(c.p, m, bit, KB, false) : 0u;
+      uint32_t proc = __popc(feas) > 1 ? choose_proc(c.p, c.w.model, m, parent, bit, KB, feas)
+                                       : (feas ? (uint32_t)(__ffs(feas) - 1) : P_LSD);
+      uint32_t sampled = 0;
       if (c.w.trace && c.p.sample_period && __popc(feas) > 1) {
         uint32_t k = atomicAdd(&S.decisions, 1u);
-        sample = ((k + blockIdx.x * 7919u) % c.p.sample_period) == 0;
+        sampled = ((k + blockIdx.x * 7919u) % c.p.sample_period) == 0 ? 1u : 0u;
       }
-      uint32_t ib = 32 - __clz(cnt - 1);
-      bool wave_ok = cnt <= c.ws && (KB - cb) + ib <= 128;
-      if (sample) code = C_CF;
-      else if (proc == P_RADIX) code = C_GRADIX;
-      else if (proc == P_BITONIC) code = wave_ok ? C_WBIT : C_GBIT;
-      else code = wave_ok ? C_WLSD : C_GLSD;
+      uint32_t slot = atomicAdd(&S.nw, 1u);
+      S.jb[slot] = js;
+      S.jn[slot] = m;
+      S.jinfo[slot] = bit | (proc << 16) | (sampled << 24) | ((feas & 7u) << 28);
+      continue;
     }
-    S.ccode[slot][v] = code;
-    if (code == C_WRANK || code == C_WLSD || code == C_WBIT) S.wlist[slot][atomicAdd(&S.wn[slot], 1u)] = v;
-    else if (code == C_PUSH) {
-      uint32_t sp = atomicAdd(&S.sp, 1u);
-      if (sp < c.p.stack_cap) {
-        Bucket ch{base + S.cbase[slot][v], cnt, parent, cb, ctmp ? BF_TMP : 0u};
-        c.stack[sp] = ch;
-      } else {
-        atomicOr(&c.w.ctl->overflow, 16u);
-      }
-    } else if (code != C_NONE) S.glist[slot][atomicAdd(&S.gn[slot], 1u)] = v;
-  }
-  __syncthreads();
-  // wavefront phase
-  {
-    const uint32_t wave = threadIdx.x / 64;
-    uint32_t* reg = c.dyn + wave * (c.ws * RW + 4 * c.ws + RB);
-    const uint32_t wn = S.wn[slot];
-    for (;;) {
-      uint32_t j = 0;
-      if (lane_id() == 0) j = atomicAdd(&S.wnext[slot], 1u);
-      j = __shfl(j, 0);
-      if (j >= wn) break;
-      uint32_t v = S.wlist[slot][j];
-      uint32_t cnt = S.ccnt[slot][v];
-      uint32_t code = S.ccode[slot][v];
-      uint64_t cbeg = base + S.cbase[slot][v];
-      uint64_t t0 = c.w.trace ? now_ticks() : 0;
-      if (code == C_WRANK) wave_rank<RW>(c, cbeg, cnt, ctmp);
-      else wave_sort<RW>(c, cbeg, cnt, ctmp, code == C_WBIT ? P_BITONIC : P_LSD, reg);
-      if (c.w.trace && code != C_WRANK && lane_id() == 0) {
-        uint32_t proc = code == C_WBIT ? P_BITONIC : P_LSD;
-        uint32_t ticks[3] = {0, 0, 0};
-        ticks[proc] = (uint32_t)((now_ticks() - t0 + 2) / 4);  // one wave of four
-        trace_row(c, cnt, parent, cb, proc, 1u << proc, ticks, 0u);
-      }
+    if (DEFER) {
+      uint32_t i = atomicAdd(&c.w.ctl->nwg, 1u);
+      if (i < c.p.cap_wg) c.w.wgjobs[i] = Bucket{S.cbegin + js, m, parent, bit, ctmp ? BF_TMP : 0u};
+      else atomicOr(&c.w.ctl->overflow, 32u);
+    } else {
+      uint32_t g = atomicAdd(&S.ng, 1u);
+      S.glist[g] = (uint16_t)j;
+      S.gjb[g] = js;
+      S.gjn[g] = m;
+      S.gbit[g] = bit;
     }
   }
   __syncthreads();
-  // workgroup phase
-  const uint32_t gn = S.gn[slot];
-  for (uint32_t j = 0; j < gn; j++) {
-    uint32_t v = S.glist[slot][j];
-    uint32_t cnt = S.ccnt[slot][v];
-    uint32_t code = S.ccode[slot][v];
-    uint64_t cbeg = base + S.cbase[slot][v];
-    if (code == C_GCOPY) {
-      wg_copy<RW>(c, cbeg, cnt);
-      __syncthreads();
+}
+
+// Wavefront jobs: each wave takes the next job (no workgroup barrier); a job
+// of at most 32 records is ranked (the insertion-sort slot of the paper),
+// others get the chosen procedure -- or, if sampled, every feasible one in
+// turn with the chosen one last, each timed.
+template <int RW>
+__device__ __forceinline__ void run_wave_jobs(Ctx& c) {
+  SmallShared& S = *c.S;
+  const uint32_t WSC = c.p.wave_cap;
+  const uint32_t wave = threadIdx.x / 64;
+  uint32_t* reg = c.dyn + wave * (WSC * RW + 4 * WSC + RB);
+  const uint32_t nw = S.nw;
+  const bool ctmp = S.ctmp != 0;
+  const uint64_t base = S.cbegin;
+  const uint64_t parent = S.cparent;
+  for (;;) {
+    uint32_t i = 0;
+    if (lane_id() == 0) i = atomicAdd(&S.wnext, 1u);
+    i = __shfl(i, 0);
+    if (i >= nw) break;
+    const uint32_t m = S.jn[i];
+    const uint32_t info = S.jinfo[i];
+    const uint64_t jb = base + S.jb[i];
+    if (m <= TINY_MAX) {
+      wave_rank<RW>(c, jb, m, ctmp);
       continue;
     }
-    uint32_t proc = code == C_GRADIX ? P_RADIX : (code == C_GBIT ? P_BITONIC : (code == C_GLSD ? P_LSD : 0xFFu));
-    if (code == C_CF) {
-      // counterfactual sample: run every feasible procedure on the same
-      // input (kept in tmp), timing each; the last run leaves the output
-      uint32_t feas = feasible_mask(c.p, cnt, cb, KB, slot == 0);
-      uint32_t chosen = choose_proc(c.p, c.w.model, cnt, parent, cb, KB, feas);
-      bool in_tmp = ctmp;
-      if (!in_tmp) {
-        for (uint64_t q = threadIdx.x; q < cnt; q += WG)
-          store_rec<RW>(c.rec1, cbeg + q, load_rec<RW>(c.rec0, cbeg + q), false);
-        __syncthreads();
-        in_tmp = true;
-      }
-      uint32_t ticks[3] = {0, 0, 0};
-      for (uint32_t k = 0; k < 3; k++) {
-        uint32_t q = (chosen + 1 + k) % 3;  // chosen procedure runs last
-        if (!((feas >> q) & 1u)) continue;
-        __syncthreads();
-        uint64_t t0 = now_ticks();
-        run_wg_proc<RW, slot == 0>(c, q, cbeg, cnt, cb, in_tmp, parent);
-        __syncthreads();
-        ticks[q] = (uint32_t)(now_ticks() - t0);
-      }
-      if (threadIdx.x == 0) trace_row(c, cnt, parent, cb, chosen, feas, ticks, 1u);
-      __syncthreads();
-      continue;
+    const uint32_t bit = info & 0xFFu, proc = (info >> 16) & 0xFu, feas = (info >> 28) & 7u;
+    const bool cf = (info >> 24) & 1u;
+    uint32_t ticks[3] = {0, 0, 0};
+    const uint32_t runs = cf ? 3u : 1u;
+#pragma unroll 1
+    for (uint32_t k = 1; k <= runs; k++) {
+      const uint32_t q = cf ? (proc + k) % 3 : proc;
+      if (cf && !((feas >> q) & 1u)) continue;
+      uint64_t t0 = now_ticks();
+      wave_sort<RW>(c, jb, m, ctmp, q, reg);
+      ticks[q] = (uint32_t)((now_ticks() - t0 + 2) / 4);  // one wave of four
     }
-    uint64_t t0 = c.w.trace ? now_ticks() : 0;
-    run_wg_proc<RW, slot == 0>(c, proc, cbeg, cnt, cb, ctmp, parent);
-    if (c.w.trace && threadIdx.x == 0) {
-      uint32_t ticks[3] = {0, 0, 0};
-      ticks[proc] = (uint32_t)(now_ticks() - t0);
-      trace_row(c, cnt, parent, cb, proc, 1u << proc, ticks, 0u);
-    }
-    __syncthreads();
+    if (c.w.trace && __popc(feas) > 1 && lane_id() == 0)
+      trace_row(c, m, parent, bit, proc, cf ? feas : (1u << proc), ticks, cf ? 1u : 0u);
+  }
+  __syncthreads();
+}
+
+// Finish the children of the last radix pass.
+template <int RW, bool DEFER>
+__device__ __forceinline__ void finish_children(Ctx& c) {
+  build_jobs<RW, DEFER>(c);
+  run_wave_jobs<RW>(c);
+  if constexpr (!DEFER) {
+    SmallShared& S = *c.S;
+    const uint32_t ng = S.ng;
+    const bool ctmp = S.ctmp != 0;
+    const uint64_t base = S.cbegin;
+    const uint64_t parent = S.cparent;
+#pragma unroll 1
+    for (uint32_t i = 0; i < ng; i++)
+      schedule_job<RW, false>(c, base + S.gjb[i], S.gjn[i], S.gbit[i], ctmp, parent);
   }
 }
 
-// A procedure run by the whole workgroup on a bucket of m <= c_fin records.
-// RADIX here is one pass whose children are all finished right away.
+// A job of m <= C records.  RADIX here is one pass whose children are all
+// finished right away.
 template <int RW, bool ALLOW_RADIX>
-__device__ void run_wg_proc(Ctx& c, uint32_t proc, uint64_t begin, uint32_t m, uint32_t bit, bool in_tmp,
-                            uint64_t parent) {
+__device__ __forceinline__ void run_job(Ctx& c, uint32_t proc, uint64_t begin, uint32_t m, uint32_t bit, bool in_tmp,
+                                        uint64_t parent) {
   if constexpr (ALLOW_RADIX) {
     if (proc == P_RADIX) {
       Bucket b{begin, m, parent, bit, in_tmp ? BF_TMP : 0u};
-      if (block_pass<RW>(c, b, 1)) handle_children<RW, 1>(c);
+      if (block_pass<RW>(c, b)) finish_children<RW, false>(c);
       return;
     }
   }
-  const bool wave_ok = m <= c.ws && (c.kf.kbits - bit) + (32 - __clz(m - 1)) <= 128;
-  if (wave_ok) {
-    if (threadIdx.x < 64) wave_sort<RW>(c, begin, m, in_tmp, proc == P_BITONIC ? P_BITONIC : P_LSD, c.dyn);
-    __syncthreads();
-  } else if (proc == P_BITONIC) {
-    wg_bitonic<RW>(c, begin, m, in_tmp);
-  } else {
-    wg_lsd<RW>(c, begin, m, in_tmp);
-  }
+  wg_finish<RW>(c, begin, m, in_tmp, proc == P_BITONIC ? P_BITONIC : P_LSD);
 }
 
-// A bucket taken from the queue or from the workgroup's stack.
-template <int RW>
-__device__ void process_root(Ctx& c, const Bucket& b) {
-  const uint32_t KB = c.kf.kbits;
-  const uint32_t m = (uint32_t)b.count;
-  const bool in_tmp = b.flags & BF_TMP;
-  if (m <= TINY_MAX) {
-    if (threadIdx.x < 64) wave_rank<RW>(c, b.begin, m, in_tmp);
-    __syncthreads();
-    return;
-  }
-  if (m > c.p.c_fin) {
-    if (block_pass<RW>(c, b, 0)) handle_children<RW, 0>(c);
-    return;
-  }
-  uint32_t feas = feasible_mask(c.p, m, b.bit, KB, true);
-  uint32_t proc = choose_proc(c.p, c.w.model, m, b.parent, b.bit, KB, feas);
-  uint64_t t0 = c.w.trace ? now_ticks() : 0;
-  run_wg_proc<RW, true>(c, proc, b.begin, m, b.bit, in_tmp, b.parent);
-  if (c.w.trace && threadIdx.x == 0 && __popc(feas) > 1) {
-    uint32_t ticks[3] = {0, 0, 0};
-    ticks[proc] = (uint32_t)(now_ticks() - t0);
-    trace_row(c, m, b.parent, b.bit, proc, 1u << proc, ticks, 0u);
-  }
-  __syncthreads();
-}
-
-template <int RW>
-__global__ __launch_bounds__(WG) void k_small(Plan p, Work w, uint8_t* rec0, uint8_t* rec1) {
-  extern __shared__ __align__(16) uint32_t dyn[];
-  __shared__ SmallShared S;
-  Ctx c;
+__device__ __forceinline__ void init_ctx(Ctx& c, const Plan& p, const Work& w, uint8_t* rec0, uint8_t* rec1,
+                                         SmallShared* S, uint32_t* dyn) {
   c.p = p;
   c.w = w;
   c.rec0 = rec0;
   c.rec1 = rec1;
   c.kf = make_keyfmt(p.key_bytes);
-  c.S = &S;
+  c.S = S;
   c.dyn = dyn;
   c.stack = w.stacks + (uint64_t)blockIdx.x * p.stack_cap;
-  c.ws = p.wave_cap;
-  if (threadIdx.x == 0) { S.sp = 0; S.decisions = 0; }
+  if (threadIdx.x == 0) { S->sp = 0; S->decisions = 0; }
   __syncthreads();
+}
+
+// Pass A: buckets above C records (radix pass, then their children) from the
+// queue and the stack; tiny buckets; everything else is deferred to pass B.
+template <int RW>
+__global__ __launch_bounds__(WG) void k_small(Plan p, Work w, uint8_t* rec0, uint8_t* rec1) {
+  extern __shared__ __align__(16) uint32_t dyn[];
+  __shared__ SmallShared S;
+  Ctx c;
+  init_ctx(c, p, w, rec0, rec1, &S, dyn);
   const uint32_t ns = (uint32_t)min((uint64_t)w.ctl->nsmall, p.cap_small);
   for (;;) {
     if (threadIdx.x == 0) S.bcast = atomicAdd(&w.ctl->small_head, 1u);
@@ -800,7 +933,19 @@ __global__ __launch_bounds__(WG) void k_small(Plan p, Work w, uint8_t* rec0, uin
     __syncthreads();
     if (idx >= ns) break;
     Bucket b = w.small_ord[idx];
-    process_root<RW>(c, b);
+    if (b.count <= p.c_fin) {
+      if (b.count <= TINY_MAX) {
+        if (threadIdx.x < 64) wave_rank<RW>(c, b.begin, (uint32_t)b.count, (b.flags & BF_TMP) != 0);
+      } else if (threadIdx.x == 0) {
+        uint32_t i = atomicAdd(&w.ctl->nwg, 1u);
+        b.flags |= BF_ROOT;
+        if (i < p.cap_wg) w.wgjobs[i] = b;
+        else atomicOr(&w.ctl->overflow, 32u);
+      }
+      __syncthreads();
+      continue;
+    }
+    if (block_pass<RW>(c, b)) finish_children<RW, true>(c);
     for (;;) {
       __syncthreads();
       if (S.sp == 0) break;
@@ -812,7 +957,7 @@ __global__ __launch_bounds__(WG) void k_small(Plan p, Work w, uint8_t* rec0, uin
       }
       __syncthreads();
       Bucket b2 = S.item;
-      process_root<RW>(c, b2);
+      if (block_pass<RW>(c, b2)) finish_children<RW, true>(c);
     }
   }
   // tiny buckets, one wavefront each
@@ -830,18 +975,46 @@ __global__ __launch_bounds__(WG) void k_small(Plan p, Work w, uint8_t* rec0, uin
   }
 }
 
+// Pass B: jobs of at most C records -- queued buckets (any procedure,
+// including one more radix pass) and children deferred by pass A.
+template <int RW>
+__global__ __launch_bounds__(WG) void k_small_jobs(Plan p, Work w, uint8_t* rec0, uint8_t* rec1) {
+  extern __shared__ __align__(16) uint32_t dyn[];
+  __shared__ SmallShared S;
+  Ctx c;
+  init_ctx(c, p, w, rec0, rec1, &S, dyn);
+  const uint32_t nj = (uint32_t)min((uint64_t)w.ctl->nwg, p.cap_wg);
+  for (;;) {
+    if (threadIdx.x == 0) S.bcast = atomicAdd(&w.ctl->wg_head, 1u);
+    __syncthreads();
+    const uint32_t idx = S.bcast;
+    __syncthreads();
+    if (idx >= nj) break;
+    const Bucket b = w.wgjobs[idx];
+    const bool in_tmp = (b.flags & BF_TMP) != 0;
+    if (b.flags & BF_ROOT) schedule_job<RW, true>(c, b.begin, (uint32_t)b.count, b.bit, in_tmp, b.parent);
+    else schedule_job<RW, false>(c, b.begin, (uint32_t)b.count, b.bit, in_tmp, b.parent);
+  }
+}
+
 uint32_t small_dynamic_lds(const Plan& p) {
   uint32_t r = p.rec_bytes;
   uint32_t block = p.block_tile * r;
-  uint32_t fin = p.c_fin * r + max(4u * p.c_fin, 16u * p.bitonic_max);
+  uint32_t fin = p.c_fin * r + 16u * p.c_fin;
   uint32_t waves = NWAVES * (p.wave_cap * r + 16u * p.wave_cap + 4u * RB);
   return max(block, max(fin, waves));
 }
 
 void launch_small(const Plan& p, const Work& w, void* records, void* tmp, hipStream_t s) {
   uint32_t lds = small_dynamic_lds(p);
+  uint8_t* r0 = (uint8_t*)records;
+  uint8_t* r1 = (uint8_t*)tmp;
   switch (p.rw) {
-#define RD_CASE(n) case n: k_small<n><<<p.grid_small, WG, lds, s>>>(p, w, (uint8_t*)records, (uint8_t*)tmp); break;
+#define RD_CASE(n)                                                   \
+  case n:                                                            \
+    k_small<n><<<p.grid_small, WG, lds, s>>>(p, w, r0, r1);          \
+    k_small_jobs<n><<<p.grid_small, WG, lds, s>>>(p, w, r0, r1);     \
+    break;
     RD_CASE(1) RD_CASE(2) RD_CASE(3) RD_CASE(4) RD_CASE(5) RD_CASE(6) RD_CASE(7) RD_CASE(8)
     RD_CASE(9) RD_CASE(10) RD_CASE(11) RD_CASE(12) RD_CASE(13) RD_CASE(14) RD_CASE(15) RD_CASE(16)
 #undef RD_CASE

@@ -202,6 +202,19 @@ __device__ __forceinline__ uint32_t common_prefix_bits(Key v, uint32_t kbits) {
 
 // ---- wavefront helpers ----------------------------------------------------
 
+// Values that are the same in every lane but come from memory (bucket
+// descriptors, counts read from LDS) are read into scalar registers, so the
+// compiler treats branches and loop bounds on them as uniform.
+__device__ __forceinline__ uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ uint64_t uni64(uint64_t x) {
+  return ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(x >> 32)) << 32) |
+         __builtin_amdgcn_readfirstlane((uint32_t)x);
+}
+__device__ __forceinline__ Key uni_key(Key k) { return Key{uni64(k.lo), uni64(k.hi)}; }
+__device__ __forceinline__ Bucket uni_bucket(const Bucket& b) {
+  return Bucket{uni64(b.begin), uni64(b.count), uni64(b.parent), uni(b.bit), uni(b.flags)};
+}
+
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
 __device__ __forceinline__ uint64_t lanemask_lt() {
@@ -217,6 +230,33 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t v, uint32_t d, uint64_t
     peers &= ((v >> b) & 1u) ? bal : ~bal;
   }
   return peers;
+}
+
+// Stable rank among equal digits, in two steps so that the LDS round trips
+// of several rounds overlap.  rank_issue: the lanes holding digit v in this
+// round ("peers") elect their lowest lane, which adds the peer count to the
+// wave's running counter wc[v] and keeps the old value; rank_finish: every
+// peer reads its leader's old value, so rank = (digit v in earlier rounds) +
+// (peers in lower lanes).  Rounds must be issued in order.
+struct RankPart {
+  uint32_t old;    // counter before this round (leader lanes)
+  uint32_t info;   // lower 16 bits: peers below this lane; upper: leader lane
+};
+
+__device__ __forceinline__ RankPart rank_issue(uint32_t* wc, uint32_t v, uint32_t d, bool valid) {
+  uint64_t active = __ballot(valid);
+  uint64_t peers = match_digit(v, d, active);
+  uint32_t lane = __lane_id();
+  uint32_t leader = valid ? (uint32_t)(__ffsll((long long)peers) - 1) : lane;
+  uint32_t old = 0;
+  if (valid && leader == lane) old = atomicAdd(&wc[v], (uint32_t)__popcll(peers));
+  uint64_t below = lane == 0 ? 0ull : (peers & (~0ull >> (64 - lane)));
+  return RankPart{old, (uint32_t)__popcll(below) | (leader << 16)};
+}
+
+__device__ __forceinline__ uint32_t rank_finish(RankPart r) {
+  uint32_t base = __shfl(r.old, (int)(r.info >> 16));
+  return base + (r.info & 0xFFFFu);
 }
 
 __device__ __forceinline__ uint64_t wave_or64(uint64_t x) {

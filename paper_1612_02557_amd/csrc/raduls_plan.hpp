@@ -16,6 +16,7 @@ struct Bucket {
 };
 constexpr uint32_t BF_TMP = 1u;
 constexpr uint32_t BF_SKIP = 2u;
+constexpr uint32_t BF_ROOT = 4u;  // deferred job that is a queued bucket (one more radix pass allowed)
 
 constexpr uint32_t LMAX = 20;        // multi-workgroup levels a plan may launch
 constexpr uint32_t TINY_MAX = 32;    // buckets this small go to one wavefront (Sec. 3.5: N <= 32)
@@ -31,13 +32,15 @@ struct Ctl {
   uint32_t nsmall;             // queued single-workgroup buckets
   uint32_t ntiny;              // queued tiny buckets
   uint32_t ncopy;              // buckets to copy from tmp to records
-  uint32_t small_head;         // queue cursors of the persistent kernel
+  uint32_t small_head;         // queue cursors of the persistent kernels
   uint32_t tiny_head;
+  uint32_t nwg;                // deferred workgroup jobs
+  uint32_t wg_head;
   uint32_t class_count[NCLASS];
   uint64_t copy_tiles;
   uint32_t copy_ticket;
   uint32_t error;              // bit 0: bad segment offsets, bit 1: look-back wait limit
-  uint32_t overflow;           // bit 0 big list, 1 small, 2 tiny, 3 copy, 4 stack
+  uint32_t overflow;           // bit 0 big list, 1 small, 2 tiny, 3 copy, 4 stack, 5 deferred jobs
   uint32_t epoch;              // look-back epoch of level 0 of this sort
 };
 
@@ -48,6 +51,7 @@ struct Plan {
   uint64_t cap_small;      // entries of the single-workgroup queue
   uint64_t cap_tiny;
   uint64_t cap_copy;
+  uint64_t cap_wg;         // deferred workgroup jobs
   uint64_t max_tiles;      // tiles of one level, upper bound
   uint32_t rec_bytes, key_bytes, rw;
   uint32_t d_big, d_block; // digit widths
@@ -84,6 +88,7 @@ struct Work {
   Bucket* copy;        // cap_copy
   uint64_t* copy_start;       // cap_copy + 1
   Bucket* stacks;      // grid_small x stack_cap
+  Bucket* wgjobs;             // cap_wg deferred workgroup jobs
   const float* model;         // scheduler network + feature normalisation, or null
   raduls_trace_row* trace;
   uint64_t* trace_count;
