@@ -79,8 +79,12 @@ typedef struct raduls_tuning {
   uint32_t lds_finish_max;    /* largest bucket finished inside LDS (0 = as large as LDS allows) */
   uint32_t bitonic_max;       /* largest bucket the bitonic finish accepts (0 = the LDS capacity) */
   uint32_t workgroups_per_cu; /* resident workgroups per CU assumed by the big threshold, 1..8 */
-  uint64_t big_min;           /* big buckets hold more than max(2N/(3W), big_min) records */
+  uint64_t big_min;           /* big buckets hold more than big_min records (and see big_rule) */
   uint32_t nontemporal;       /* 1: non-temporal stores for scattered output */
+  uint32_t big_rule;          /* 0: also more than 2N/(3W) (Sec. 3.2, W = resident workgroups);
+                                 1: big_min alone */
+  uint32_t job_records;       /* children of a radix pass are grouped into finishing jobs of at
+                                 most this many records (0 = the LDS capacity) */
   uint32_t reserved;
 } raduls_tuning;
 

@@ -4,8 +4,9 @@ The paper's scheduler (Sec. 3.2-3.5) picks, per bin, how to process it from
 its size alone, with constants it chose by experiment:
   * a bin is big, and gets a multi-thread pass, when it holds more than
     2N/(3T) records (N all records, T threads), Sec. 3.2;
-  * a bin that fits in half of the L2 cache is split by a plain counting
-    pass, a larger one by the buffered split, Sec. 3.4;
+  * every other bin gets another radix pass; one that fits in half of the
+    L2 cache is split by a plain counting pass in cache, a larger one by the
+    buffered split, Sec. 3.4;
   * a bin with fewer than 384 keys is finished by a comparison sort; when the
     narrowing factor (parent size / bin size) exceeds sqrt(R) = 16 that tiny
     threshold drops to 32; insertion sort serves bins of at most 32, Sec. 3.5.
@@ -15,9 +16,11 @@ as concurrently resident workgroups and "fits in cache" as "fits the
 workgroup's local data share":
   RANK     (one wavefront, all-pairs rank; the insertion-sort slot)  m <= 32
   BITONIC  (comparison sort in LDS)             m < tiny(m, parent)
-  LSD      (counting passes inside LDS)         m <= lds_capacity
-  RADIX    (one radix pass through memory, children recursed)  otherwise
-and BIG (multi-workgroup pass) for m > 2N/(3W).
+  RADIX    (one more radix pass: inside LDS when m <= lds_capacity, its
+            sub-bins insertion sorted; through memory otherwise)
+and BIG (multi-workgroup pass) for m > 2N/(3W).  LSD (stable counting passes
+inside LDS) is a further procedure that only the learned or forced
+scheduler picks.
 """
 from __future__ import annotations
 
@@ -51,8 +54,6 @@ def heuristic(m: int, parent_m: int, bits_left: int, lds_capacity: int, bitonic_
     tiny = TINY_NARROW if narrowing > NARROW else TINY
     if m < tiny and m <= bitonic_capacity:
         return PROC_BITONIC
-    if m <= lds_capacity:
-        return PROC_LSD
     return PROC_RADIX
 
 

@@ -137,6 +137,8 @@ int validate_tuning(const raduls_tuning& t) {
   if (t.tile_records < 256 || t.tile_records > 8192 || (t.tile_records & (t.tile_records - 1)))
     return fail(RADULS_EINVAL, "tile_records must be a power of two in 256..8192");
   if (t.workgroups_per_cu < 1 || t.workgroups_per_cu > 8) return fail(RADULS_EINVAL, "workgroups_per_cu must be 1..8");
+  if (t.big_rule > 1) return fail(RADULS_EINVAL, "big_rule must be 0 or 1");
+  if (t.job_records != 0 && t.job_records < 64) return fail(RADULS_EINVAL, "job_records must be 0 or >= 64");
   return RADULS_OK;
 }
 
@@ -168,13 +170,17 @@ Plan make_plan(uint64_t n, uint32_t r, uint32_t k, const raduls_tuning& t, int c
   // wavefront jobs: four wave regions of records + 16 bytes of composites
   // per record + 256 counters each
   p.wave_cap = std::min<uint32_t>(256, ((dyn / 4 - 1024) / (r + 16)) / 64 * 64);
+  // a window of W records yields jobs of at most 2W (see build_jobs)
+  uint32_t job = t.job_records ? std::min<uint32_t>(t.job_records, cfin) : cfin;
+  p.job_window = std::max<uint32_t>(32, job / 2);
   p.nontemporal = t.nontemporal;
   p.grid_small = cus * t.workgroups_per_cu;
   p.grid_scatter = cus * 2;
   p.grid_hist = cus * 4;
   p.grid_clear = cus * 4;
   uint64_t W = p.grid_small;
-  p.t_big = std::max<uint64_t>(2 * n / (3 * W), std::max<uint64_t>(t.big_min, (uint64_t)p.c_fin));
+  p.t_big = std::max<uint64_t>(t.big_min, (uint64_t)p.c_fin);
+  if (t.big_rule == 0) p.t_big = std::max<uint64_t>(p.t_big, 2 * n / (3 * W));
   uint32_t kb = 8 * k;
   p.lmax = std::min<uint32_t>((kb + p.d_big - 1) / p.d_big + 1, rd::LMAX);
   p.cap_big = n / (p.t_big + 1) + 2;

@@ -23,6 +23,7 @@ constexpr uint32_t RB = 256;          // radix of one-workgroup passes (d_block 
 constexpr uint32_t MAX_ROUNDS = 16;   // LDS finishing capacity <= 16 * WG records
 constexpr uint32_t IPT_BLOCK = 8;     // records per thread in a radix-pass tile
 constexpr uint32_t EMAX = 4;          // records per lane of a wavefront job (at most 256)
+constexpr uint32_t INSERTION_MAX = 32; // insertion sort serves bins of at most 32 keys (Sec. 3.5)
 
 struct SmallShared {
   uint32_t hist[RB];
@@ -38,10 +39,7 @@ struct SmallShared {
   uint32_t jb[RB];        // job start (offset in the parent bucket)
   uint32_t jn[RB];        // job length
   uint32_t jinfo[RB];     // shared key bits | procedure << 16 | sampled << 24 | feasible << 28
-  uint16_t glist[RB];     // workgroup jobs
-  uint32_t gjb[RB], gjn[RB];
-  uint8_t gbit[RB];
-  uint32_t nw, ng, wnext;
+  uint32_t nw, wnext;
   uint32_t cbit, pbit, cR, ctmp;
   uint64_t cbegin, cparent;
   uint32_t sp;
@@ -290,6 +288,145 @@ __device__ __forceinline__ void wave_sort(Ctx& c, uint64_t begin, uint32_t m, bo
 }
 
 
+// wave_sort for jobs whose composite fits 64 bits ((key bits left) + index
+// bits <= 64): the same two procedures on single 64-bit values.
+template <int RW>
+__device__ __forceinline__ void wave_sort64(Ctx& c, uint64_t begin, uint32_t m, bool in_tmp, uint32_t proc,
+                                            uint32_t* reg) {
+  const uint32_t ws = c.p.wave_cap;
+  const uint32_t l = lane_id();
+  const uint8_t* src = in_tmp ? c.rec1 : c.rec0;
+  const uint32_t E = (m + 63) / 64;
+  uint32_t* recs = reg;                                        // ws * RW words
+  uint64_t* cl = reinterpret_cast<uint64_t*>(reg + ws * RW);   // ws composites
+  uint32_t* hist = reinterpret_cast<uint32_t*>(cl + 2 * ws);   // 256 counters
+  Key key[EMAX];
+#pragma unroll
+  for (uint32_t e = 0; e < EMAX; e++) {
+    uint32_t i = e * 64 + l;
+    key[e] = Key{0, 0};
+    if (e < E && i < m) {
+      Rec<RW> r = load_rec<RW>(src, begin + i);
+      lds_put<RW>(recs, i, r);
+      key[e] = rec_key<RW>(r, c.kf);
+    }
+  }
+  Key ref{__shfl(key[0].lo, 0), __shfl(key[0].hi, 0)};
+  uint64_t vlo = 0, vhi = 0;
+#pragma unroll
+  for (uint32_t e = 0; e < EMAX; e++) {
+    uint32_t i = e * 64 + l;
+    if (e < E && i < m) { vlo |= key[e].lo ^ ref.lo; vhi |= key[e].hi ^ ref.hi; }
+  }
+  Key vary{wave_or64(vlo), wave_or64(vhi)};
+  wave_lds_sync();
+  if (vary.lo == 0 && vary.hi == 0) {
+    if (in_tmp) {
+#pragma unroll
+      for (uint32_t e = 0; e < EMAX; e++) {
+        uint32_t i = e * 64 + l;
+        if (e < E && i < m) store_rec<RW>(c.rec0, begin + i, lds_get<RW>(recs, i), false);
+      }
+    }
+    return;
+  }
+  const uint32_t lo = ctz128(vary);
+  const uint32_t wv = bitlen128(vary) - lo;
+  const uint32_t ib = 32 - __clz(m - 1);
+  const uint64_t vmask = wv >= 64 ? ~0ull : ((1ull << wv) - 1);
+  uint64_t cp[EMAX];
+#pragma unroll
+  for (uint32_t e = 0; e < EMAX; e++) {
+    uint32_t i = e * 64 + l;
+    cp[e] = (e < E && i < m) ? (((shr128(key[e], lo).lo & vmask) << ib) | i) : ~0ull;
+  }
+  if (proc == P_BITONIC) {
+    const uint32_t P = 64 * (E == 3 ? 4 : E);
+    for (uint32_t k = 2; k <= P; k <<= 1) {
+      for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+        if (j >= 64) {
+          const uint32_t ej = j >> 6;
+#pragma unroll
+          for (uint32_t e = 0; e < EMAX; e++) {
+#pragma unroll
+            for (uint32_t f = e + 1; f < EMAX; f++) {
+              if (f == (e ^ ej) && f * 64 < P) {
+                bool asc = ((e * 64 + l) & k) == 0;
+                uint64_t a = cp[e], b = cp[f];
+                if ((a > b) == asc) { cp[e] = b; cp[f] = a; }
+              }
+            }
+          }
+        } else {
+          const bool lower = (l & j) == 0;
+#pragma unroll
+          for (uint32_t e = 0; e < EMAX; e++) {
+            if (e * 64 < P) {
+              uint64_t o = __shfl_xor(cp[e], (int)j);
+              bool asc = ((e * 64 + l) & k) == 0;
+              // keep the smaller value when (lower == asc), else the larger
+              if ((lower == asc) == (cp[e] > o)) cp[e] = o;
+            }
+          }
+        }
+      }
+    }
+  } else {
+    // stable counting passes over the varying bits, least significant first
+    for (uint32_t s = 0; s < wv; s += 8) {
+      const uint32_t d = min(8u, wv - s);
+      const uint32_t R = 1u << d;
+      const uint32_t sh = ib + s;
+      for (uint32_t v = l; v < R; v += 64) hist[v] = 0;
+      wave_lds_sync();
+      uint32_t dg[EMAX], rk[EMAX];
+      RankPart rp[EMAX];
+#pragma unroll
+      for (uint32_t e = 0; e < EMAX; e++) {
+        if (e < E) {
+          uint32_t i = e * 64 + l;
+          bool valid = i < m;
+          uint32_t v = (uint32_t)(cp[e] >> sh) & (R - 1);
+          rp[e] = rank_issue(hist, v, d, valid);
+          dg[e] = v;
+        }
+      }
+#pragma unroll
+      for (uint32_t e = 0; e < EMAX; e++)
+        if (e < E) rk[e] = rank_finish(rp[e]);
+      wave_lds_sync();
+      uint32_t h[4], loc = 0;
+#pragma unroll
+      for (int q = 0; q < 4; q++) { uint32_t v = l * 4 + q; h[q] = v < R ? hist[v] : 0u; loc += h[q]; }
+      uint32_t tot;
+      uint32_t ex = wave_excl_scan(loc, &tot);
+      wave_lds_sync();
+#pragma unroll
+      for (int q = 0; q < 4; q++) { uint32_t v = l * 4 + q; if (v < R) hist[v] = ex; ex += h[q]; }
+      wave_lds_sync();
+#pragma unroll
+      for (uint32_t e = 0; e < EMAX; e++) {
+        uint32_t i = e * 64 + l;
+        if (e < E && i < m) cl[hist[dg[e]] + rk[e]] = cp[e];
+      }
+      wave_lds_sync();
+#pragma unroll
+      for (uint32_t e = 0; e < EMAX; e++) {
+        uint32_t i = e * 64 + l;
+        if (e < E && i < m) cp[e] = cl[i];
+      }
+      wave_lds_sync();
+    }
+  }
+  const uint64_t imask = (1ull << ib) - 1;
+#pragma unroll
+  for (uint32_t e = 0; e < EMAX; e++) {
+    uint32_t i = e * 64 + l;
+    if (e < E && i < m) store_rec<RW>(c.rec0, begin + i, lds_get<RW>(recs, (uint32_t)(cp[e] & imask)), false);
+  }
+  wave_lds_sync();
+}
+
 // ---------------------------------------------------------------------------
 // Workgroup procedures.
 
@@ -397,22 +534,10 @@ __device__ __forceinline__ void lds_pass64(SmallShared& S, const uint64_t* src, 
 // permutation reading the keys from the stage, and BITONIC sorts 128-bit
 // composites.
 template <int RW>
-__device__ __forceinline__ void wg_finish(Ctx& c, uint64_t begin, uint32_t m, bool in_tmp, uint32_t proc) {
+__device__ __forceinline__ void wg_sort_staged(Ctx& c, uint64_t begin, uint32_t m, uint32_t proc, Key vary) {
   SmallShared& S = *c.S;
-  if (m <= 1) {
-    if (m == 1 && in_tmp && threadIdx.x == 0) store_rec<RW>(c.rec0, begin, load_rec<RW>(c.rec1, begin), false);
-    __syncthreads();
-    return;
-  }
   const uint32_t C = c.p.c_fin;
-  Key vary = wg_stage<RW>(c, begin, m, in_tmp);
   const uint32_t* stage = c.dyn;
-  if (vary.lo == 0 && vary.hi == 0) {
-    if (in_tmp)
-      for (uint32_t q = threadIdx.x; q < m; q += WG) store_rec<RW>(c.rec0, begin + q, lds_get<RW>(stage, q), false);
-    __syncthreads();
-    return;
-  }
   const uint32_t lo = ctz128(vary);
   const uint32_t W = bitlen128(vary) - lo;
   const uint32_t ib = 32 - __clz(m - 1);
@@ -535,6 +660,96 @@ __device__ __forceinline__ void wg_finish(Ctx& c, uint64_t begin, uint32_t m, bo
     uint16_t* t = perm0; perm0 = perm1; perm1 = t;
   }
   for (uint32_t q = threadIdx.x; q < m; q += WG) store_rec<RW>(c.rec0, begin + q, lds_get<RW>(stage, perm0[q]), false);
+  __syncthreads();
+}
+
+// Stage a job; returns false when it is finished already (at most one
+// record, or every key equal), after putting it in records if it lay in tmp.
+template <int RW>
+__device__ __forceinline__ bool wg_begin(Ctx& c, uint64_t begin, uint32_t m, bool in_tmp, Key& vary) {
+  if (m <= 1) {
+    if (m == 1 && in_tmp && threadIdx.x == 0) store_rec<RW>(c.rec0, begin, load_rec<RW>(c.rec1, begin), false);
+    __syncthreads();
+    return false;
+  }
+  vary = wg_stage<RW>(c, begin, m, in_tmp);
+  if (vary.lo == 0 && vary.hi == 0) {
+    if (in_tmp)
+      for (uint32_t q = threadIdx.x; q < m; q += WG) store_rec<RW>(c.rec0, begin + q, lds_get<RW>(c.dyn, q), false);
+    __syncthreads();
+    return false;
+  }
+  return true;
+}
+
+template <int RW>
+__device__ __forceinline__ void wg_finish(Ctx& c, uint64_t begin, uint32_t m, bool in_tmp, uint32_t proc) {
+  Key vary;
+  if (wg_begin<RW>(c, begin, m, in_tmp, vary)) wg_sort_staged<RW>(c, begin, m, proc, vary);
+}
+
+// RADIX on a job that fits LDS: the next radix pass of the bin is made in
+// fast memory and the bins it yields, at most 32 keys each, are insertion
+// sorted (paper, Sec. 3.4-3.5).  The composites (varying key bits << ib |
+// local index) are counted by their top D <= 10 bits, placed in digit order
+// (any order within a digit), and each thread insertion-sorts the
+// sub-buckets it owns; the composites are unique, so the result is the
+// stable order.  A sub-bucket above 32 composites (a skewed job) makes the
+// workgroup finish the job by LSD from the same stage instead.
+template <int RW>
+__device__ __forceinline__ void wg_radix_lds(Ctx& c, uint64_t begin, uint32_t m, bool in_tmp) {
+  SmallShared& S = *c.S;
+  Key vary;
+  if (!wg_begin<RW>(c, begin, m, in_tmp, vary)) return;
+  const uint32_t lo = ctz128(vary);
+  const uint32_t W = bitlen128(vary) - lo;
+  const uint32_t ib = 32 - __clz(m - 1);
+  if (W + ib > 64) {
+    wg_sort_staged<RW>(c, begin, m, P_LSD, vary);
+    return;
+  }
+  const uint32_t C = c.p.c_fin;
+  const uint32_t* stage = c.dyn;
+  uint64_t* c0 = reinterpret_cast<uint64_t*>(c.dyn + C * RW);
+  uint64_t* c1 = c0 + C;
+  const uint32_t D = min(10u, W);
+  const uint32_t R = 1u << D;
+  const uint32_t dsh = ib + W - D;
+  const uint64_t wmask = W >= 64 ? ~0ull : ((1ull << W) - 1);
+  uint32_t* cnt = S.wcnt;  // NWAVES * RB >= 1024 counters
+  for (uint32_t v = threadIdx.x; v < R; v += WG) cnt[v] = 0;
+  __syncthreads();
+  for (uint32_t q = threadIdx.x; q < m; q += WG) {
+    uint64_t x = ((shr128(lds_key<RW>(stage, q, c.kf), lo).lo & wmask) << ib) | q;
+    c0[q] = x;
+    atomicAdd(&cnt[(uint32_t)(x >> dsh)], 1u);
+  }
+  __syncthreads();
+  block_excl_scan_lds(cnt, R, S.scan_tmp);
+  for (uint32_t q = threadIdx.x; q < m; q += WG) {
+    uint64_t x = c0[q];
+    c1[atomicAdd(&cnt[(uint32_t)(x >> dsh)], 1u)] = x;
+  }
+  __syncthreads();
+  // cnt[v] is now the end of sub-bucket v
+  int big = 0;
+  for (uint32_t v = threadIdx.x; v < R; v += WG) {
+    const uint32_t s0 = v ? cnt[v - 1] : 0u, e = cnt[v];
+    if (e - s0 > INSERTION_MAX) { big = 1; continue; }
+    for (uint32_t i = s0 + 1; i < e; i++) {
+      uint64_t x = c1[i];
+      uint32_t j = i;
+      while (j > s0 && c1[j - 1] > x) { c1[j] = c1[j - 1]; j--; }
+      c1[j] = x;
+    }
+  }
+  if (__syncthreads_or(big)) {
+    wg_sort_staged<RW>(c, begin, m, P_LSD, vary);
+    return;
+  }
+  const uint64_t imask = (1ull << ib) - 1;
+  for (uint32_t q = threadIdx.x; q < m; q += WG)
+    store_rec<RW>(c.rec0, begin + q, lds_get<RW>(stage, (uint32_t)(c1[q] & imask)), false);
   __syncthreads();
 }
 
@@ -687,9 +902,8 @@ __device__ __forceinline__ void trace_row(Ctx& c, uint64_t m, uint64_t parent, u
   c.w.trace[i] = row;
 }
 
-template <int RW, bool ALLOW_RADIX>
-__device__ __forceinline__ void run_job(Ctx& c, uint32_t proc, uint64_t begin, uint32_t m, uint32_t bit, bool in_tmp,
-                                        uint64_t parent);
+template <int RW>
+__device__ __forceinline__ void run_job(Ctx& c, uint32_t proc, uint64_t begin, uint32_t m, bool in_tmp);
 
 // Is this job sampled for counterfactual timing?  (Workgroup-uniform.)
 __device__ __forceinline__ bool sample_job(Ctx& c, uint32_t feas) {
@@ -711,11 +925,11 @@ __device__ __forceinline__ bool sample_job(Ctx& c, uint32_t feas) {
 // procedure runs in turn on the same input (each is a complete stable sort,
 // so later runs see input that is already in order and rewrite the same
 // bytes) and the chosen one runs last.
-template <int RW, bool ALLOW_RADIX>
+template <int RW>
 __device__ __forceinline__ void schedule_job(Ctx& c, uint64_t begin, uint32_t m, uint32_t bit, bool in_tmp,
                                              uint64_t parent) {
   const uint32_t KB = c.kf.kbits;
-  const uint32_t feas = feasible_mask(c.p, m, bit, KB, ALLOW_RADIX);
+  const uint32_t feas = feasible_mask(c.p, m, bit, KB, true);
   const uint32_t proc = choose_proc(c.p, c.w.model, m, parent, bit, KB, feas);
   const bool cf = sample_job(c, feas);
   const uint32_t runs = cf ? 3u : 1u;
@@ -726,7 +940,7 @@ __device__ __forceinline__ void schedule_job(Ctx& c, uint64_t begin, uint32_t m,
     if (!((feas >> q) & 1u) && cf) continue;
     __syncthreads();
     uint64_t t0 = now_ticks();
-    run_job<RW, ALLOW_RADIX>(c, q, begin, m, bit, in_tmp, parent);
+    run_job<RW>(c, q, begin, m, in_tmp);
     __syncthreads();
     ticks[q] = (uint32_t)(now_ticks() - t0);
   }
@@ -738,18 +952,18 @@ __device__ __forceinline__ void schedule_job(Ctx& c, uint64_t begin, uint32_t m,
 // Group the children of the last radix pass into finishing jobs.  Children
 // lie consecutively in key order, so a run of whole children is a valid job:
 // sorting the run by key sorts each child and leaves the children in place.
-// With T = half the wavefront capacity, a child above T is a job of its own
+// With T = the job window (at most C/2), a child above T is a job of its own
 // and smaller children are grouped by the T-window their first record falls
-// in, so a group holds at most 2T records.  Jobs of at most the wavefront
-// capacity go to the wavefront list; larger ones (single children of at most
-// C records) to the workgroup list, or are deferred to the global list; a
-// child above C goes to the workgroup's stack.  All threads take part.
-template <int RW, bool DEFER>
+// in, so a group holds at most 2T <= C records.  Jobs of at most the
+// wavefront capacity go to the wavefront list, larger ones are deferred to
+// the global workgroup-job list, and a child above C goes to the
+// workgroup's stack.  All threads take part.
+template <int RW>
 __device__ __forceinline__ void build_jobs(Ctx& c) {
   SmallShared& S = *c.S;
   const uint32_t C = c.p.c_fin;
   const uint32_t WSC = c.p.wave_cap;
-  const uint32_t T = WSC / 2;
+  const uint32_t T = c.p.job_window;
   const uint32_t KB = c.kf.kbits;
   const uint32_t R = S.cR;
   const uint32_t t = threadIdx.x;
@@ -757,7 +971,7 @@ __device__ __forceinline__ void build_jobs(Ctx& c) {
   const uint32_t cnt = t < R ? S.ccnt[t] : 0u;
   const uint32_t st = t < R ? S.cbase[t] : 0u;
   S.toff[t] = cnt > 0 ? 1u : 0u;
-  if (t == 0) { S.nw = 0; S.ng = 0; S.wnext = 0; }
+  if (t == 0) { S.nw = 0; S.wnext = 0; }
   __syncthreads();
   const uint32_t nn = block_excl_scan_lds(S.toff, WG, S.scan_tmp);
   if (cnt > 0) { S.jb[S.toff[t]] = st; S.jn[S.toff[t]] = cnt; }
@@ -812,17 +1026,9 @@ __device__ __forceinline__ void build_jobs(Ctx& c) {
       S.jinfo[slot] = bit | (proc << 16) | (sampled << 24) | ((feas & 7u) << 28);
       continue;
     }
-    if (DEFER) {
-      uint32_t i = atomicAdd(&c.w.ctl->nwg, 1u);
-      if (i < c.p.cap_wg) c.w.wgjobs[i] = Bucket{S.cbegin + js, m, parent, bit, ctmp ? BF_TMP : 0u};
-      else atomicOr(&c.w.ctl->overflow, 32u);
-    } else {
-      uint32_t g = atomicAdd(&S.ng, 1u);
-      S.glist[g] = (uint16_t)j;
-      S.gjb[g] = js;
-      S.gjn[g] = m;
-      S.gbit[g] = bit;
-    }
+    uint32_t i = atomicAdd(&c.w.ctl->nwg, 1u);
+    if (i < c.p.cap_wg) c.w.wgjobs[i] = Bucket{S.cbegin + js, m, parent, bit, ctmp ? BF_TMP : 0u};
+    else atomicOr(&c.w.ctl->overflow, 32u);
   }
   __syncthreads();
 }
@@ -857,12 +1063,14 @@ __device__ __forceinline__ void run_wave_jobs(Ctx& c) {
     const bool cf = (info >> 24) & 1u;
     uint32_t ticks[3] = {0, 0, 0};
     const uint32_t runs = cf ? 3u : 1u;
+    const bool narrow = (c.kf.kbits - bit) + (32 - __clz(m - 1)) <= 64;
 #pragma unroll 1
     for (uint32_t k = 1; k <= runs; k++) {
       const uint32_t q = cf ? (proc + k) % 3 : proc;
       if (cf && !((feas >> q) & 1u)) continue;
       uint64_t t0 = now_ticks();
-      wave_sort<RW>(c, jb, m, ctmp, q, reg);
+      if (narrow) wave_sort64<RW>(c, jb, m, ctmp, q, reg);
+      else wave_sort<RW>(c, jb, m, ctmp, q, reg);
       ticks[q] = (uint32_t)((now_ticks() - t0 + 2) / 4);  // one wave of four
     }
     if (c.w.trace && __popc(feas) > 1 && lane_id() == 0)
@@ -871,36 +1079,19 @@ __device__ __forceinline__ void run_wave_jobs(Ctx& c) {
   __syncthreads();
 }
 
-// Finish the children of the last radix pass.
-template <int RW, bool DEFER>
+// Finish the children of the last radix pass: wavefront jobs now, workgroup
+// jobs deferred to the jobs kernel.
+template <int RW>
 __device__ __forceinline__ void finish_children(Ctx& c) {
-  build_jobs<RW, DEFER>(c);
+  build_jobs<RW>(c);
   run_wave_jobs<RW>(c);
-  if constexpr (!DEFER) {
-    SmallShared& S = *c.S;
-    const uint32_t ng = S.ng;
-    const bool ctmp = S.ctmp != 0;
-    const uint64_t base = S.cbegin;
-    const uint64_t parent = S.cparent;
-#pragma unroll 1
-    for (uint32_t i = 0; i < ng; i++)
-      schedule_job<RW, false>(c, base + S.gjb[i], S.gjn[i], S.gbit[i], ctmp, parent);
-  }
 }
 
-// A job of m <= C records.  RADIX here is one pass whose children are all
-// finished right away.
-template <int RW, bool ALLOW_RADIX>
-__device__ __forceinline__ void run_job(Ctx& c, uint32_t proc, uint64_t begin, uint32_t m, uint32_t bit, bool in_tmp,
-                                        uint64_t parent) {
-  if constexpr (ALLOW_RADIX) {
-    if (proc == P_RADIX) {
-      Bucket b{begin, m, parent, bit, in_tmp ? BF_TMP : 0u};
-      if (block_pass<RW>(c, b)) finish_children<RW, false>(c);
-      return;
-    }
-  }
-  wg_finish<RW>(c, begin, m, in_tmp, proc == P_BITONIC ? P_BITONIC : P_LSD);
+// A job of m <= C records by the chosen procedure.
+template <int RW>
+__device__ __forceinline__ void run_job(Ctx& c, uint32_t proc, uint64_t begin, uint32_t m, bool in_tmp) {
+  if (proc == P_RADIX) wg_radix_lds<RW>(c, begin, m, in_tmp);
+  else wg_finish<RW>(c, begin, m, in_tmp, proc == P_BITONIC ? P_BITONIC : P_LSD);
 }
 
 __device__ __forceinline__ void init_ctx(Ctx& c, const Plan& p, const Work& w, uint8_t* rec0, uint8_t* rec1,
@@ -945,7 +1136,7 @@ __global__ __launch_bounds__(WG) void k_small(Plan p, Work w, uint8_t* rec0, uin
       __syncthreads();
       continue;
     }
-    if (block_pass<RW>(c, b)) finish_children<RW, true>(c);
+    if (block_pass<RW>(c, b)) finish_children<RW>(c);
     for (;;) {
       __syncthreads();
       if (S.sp == 0) break;
@@ -957,7 +1148,7 @@ __global__ __launch_bounds__(WG) void k_small(Plan p, Work w, uint8_t* rec0, uin
       }
       __syncthreads();
       Bucket b2 = S.item;
-      if (block_pass<RW>(c, b2)) finish_children<RW, true>(c);
+      if (block_pass<RW>(c, b2)) finish_children<RW>(c);
     }
   }
   // tiny buckets, one wavefront each
@@ -975,8 +1166,8 @@ __global__ __launch_bounds__(WG) void k_small(Plan p, Work w, uint8_t* rec0, uin
   }
 }
 
-// Pass B: jobs of at most C records -- queued buckets (any procedure,
-// including one more radix pass) and children deferred by pass A.
+// Pass B: jobs of at most C records -- queued buckets and groups of
+// children deferred by pass A -- each by its scheduled procedure.
 template <int RW>
 __global__ __launch_bounds__(WG) void k_small_jobs(Plan p, Work w, uint8_t* rec0, uint8_t* rec1) {
   extern __shared__ __align__(16) uint32_t dyn[];
@@ -991,9 +1182,7 @@ __global__ __launch_bounds__(WG) void k_small_jobs(Plan p, Work w, uint8_t* rec0
     __syncthreads();
     if (idx >= nj) break;
     const Bucket b = w.wgjobs[idx];
-    const bool in_tmp = (b.flags & BF_TMP) != 0;
-    if (b.flags & BF_ROOT) schedule_job<RW, true>(c, b.begin, (uint32_t)b.count, b.bit, in_tmp, b.parent);
-    else schedule_job<RW, false>(c, b.begin, (uint32_t)b.count, b.bit, in_tmp, b.parent);
+    schedule_job<RW>(c, b.begin, (uint32_t)b.count, b.bit, (b.flags & BF_TMP) != 0, b.parent);
   }
 }
 

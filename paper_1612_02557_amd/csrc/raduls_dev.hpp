@@ -202,19 +202,6 @@ __device__ __forceinline__ uint32_t common_prefix_bits(Key v, uint32_t kbits) {
 
 // ---- wavefront helpers ----------------------------------------------------
 
-// Values that are the same in every lane but come from memory (bucket
-// descriptors, counts read from LDS) are read into scalar registers, so the
-// compiler treats branches and loop bounds on them as uniform.
-__device__ __forceinline__ uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
-__device__ __forceinline__ uint64_t uni64(uint64_t x) {
-  return ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(x >> 32)) << 32) |
-         __builtin_amdgcn_readfirstlane((uint32_t)x);
-}
-__device__ __forceinline__ Key uni_key(Key k) { return Key{uni64(k.lo), uni64(k.hi)}; }
-__device__ __forceinline__ Bucket uni_bucket(const Bucket& b) {
-  return Bucket{uni64(b.begin), uni64(b.count), uni64(b.parent), uni(b.bit), uni(b.flags)};
-}
-
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
 __device__ __forceinline__ uint64_t lanemask_lt() {

@@ -64,6 +64,7 @@ struct Plan {
   uint32_t stack_cap;      // entries per workgroup stack
   uint32_t block_tile;     // records per tile of a one-workgroup pass
   uint32_t wave_cap;       // largest bucket one wavefront finishes
+  uint32_t job_window;     // children are grouped by windows of this many records
   uint32_t sched_mode, forced_proc;
   uint32_t segmented;
   uint32_t epoch;          // look-back epoch of level 0 (level l uses epoch + l)

@@ -54,13 +54,14 @@ __device__ __forceinline__ uint32_t feasible_mask(const Plan& p, uint64_t m, uin
 }
 
 // Paper rules (Sec. 3.5: tiny bins < 384 keys, < 32 when the narrowing
-// factor parent/current exceeds 16; Sec. 3.4: a bin that fits fast memory is
-// split there) restricted to the feasible procedures.
+// factor parent/current exceeds 16, get a comparison sort; Sec. 3.4: other
+// bins get another radix pass, in fast memory when they fit there)
+// restricted to the feasible procedures.
 __device__ __forceinline__ uint32_t heuristic_proc(uint64_t m, uint64_t parent, uint32_t feas) {
   uint64_t tiny = (parent > (uint64_t)H_NARROW * m) ? H_TINY_NARROW : H_TINY;
   if (m < tiny && (feas & (1u << P_BITONIC))) return P_BITONIC;
-  if (feas & (1u << P_LSD)) return P_LSD;
   if (feas & (1u << P_RADIX)) return P_RADIX;
+  if (feas & (1u << P_LSD)) return P_LSD;
   return P_BITONIC;
 }
 

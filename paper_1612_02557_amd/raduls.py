@@ -36,6 +36,8 @@ class Tuning(ctypes.Structure):
         ("workgroups_per_cu", _u32),
         ("big_min", _u64),
         ("nontemporal", _u32),
+        ("big_rule", _u32),
+        ("job_records", _u32),
         ("reserved", _u32),
     ]
 

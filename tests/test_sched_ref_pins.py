@@ -39,12 +39,12 @@ def test_rule_boundaries():
     assert h(32, 64) == S.PROC_RANK            # insertion-sort slot: N <= 32
     assert h(33, 66) == S.PROC_BITONIC         # tiny: fewer than 384 keys
     assert h(383, 766) == S.PROC_BITONIC
-    assert h(384, 768) == S.PROC_LSD           # not tiny any more (strict "<")
+    assert h(384, 768) == S.PROC_RADIX         # not tiny any more (strict "<")
     # narrowing factor above 16 lowers the tiny threshold to 32
-    assert h(100, 1601) == S.PROC_LSD
+    assert h(100, 1601) == S.PROC_RADIX
     assert h(100, 1600) == S.PROC_BITONIC      # exactly 16 is not "larger than"
-    assert h(4096, 10**6) == S.PROC_LSD
-    assert h(4097, 10**6) == S.PROC_RADIX
+    assert h(4096, 10**6) == S.PROC_RADIX      # in LDS
+    assert h(4097, 10**6) == S.PROC_RADIX      # through memory
     assert h(big, 10**9) == S.PROC_RADIX
     assert h(big + 1, 10**9) == S.PROC_BIG
 
