@@ -179,11 +179,20 @@ def main():
                 b = mult * r * recs
                 passes.append({"phase": name, "kernel": f"k_{kind}", "ms": t, "records": recs, "alg_bytes": b,
                                "GBps": b / t / 1e6 if t > 0 else None})
+    # single-workgroup queue pass: a one-workgroup radix pass reads its bucket
+    # twice (count, move) and writes it once; wavefront and tiny jobs read
+    # and write once
     if "small" in phase_acc:
         t = statistics.mean(phase_acc["small"])
-        recs = work["small"] + work["tiny"]
-        b = 2 * r * recs
+        recs = work["block_pass"] + work["wave_jobs"] + work["tiny_done"]
+        b = r * (3 * work["block_pass"] + 2 * (work["wave_jobs"] + work["tiny_done"]))
         passes.append({"phase": "small", "kernel": "k_small", "ms": t, "records": recs, "alg_bytes": b,
+                       "GBps": b / t / 1e6 if t > 0 else None})
+    if "small_jobs" in phase_acc:
+        t = statistics.mean(phase_acc["small_jobs"])
+        recs = work["wg_jobs"]
+        b = 2 * r * recs
+        passes.append({"phase": "small_jobs", "kernel": "k_small_jobs", "ms": t, "records": recs, "alg_bytes": b,
                        "GBps": b / t / 1e6 if t > 0 else None})
     other = {nm: statistics.mean(v) for nm, v in phase_acc.items()
              if not any(p["phase"] == nm for p in passes)}

@@ -176,15 +176,19 @@ int raduls_set_timing(int on);
 /* Device milliseconds of each launch group of the last raduls_sort run with
  * timing mode 2, waiting for it: index 0 setup; for level l (0..19) 1+4l
  * tile ranges and histogram reset, 2+4l histogram, 3+4l scan, 4+4l scatter;
- * 81 queue ordering, 82 single-workgroup kernel, 83 copy-back.  `count`
- * entries of host_ms are written (84 cover every phase). */
-#define RADULS_PHASES 84
+ * 81 queue ordering, 82 single-workgroup queue pass, 83 single-workgroup
+ * jobs pass, 84 copy-back.  `count` entries of host_ms are written (85 cover
+ * every phase). */
+#define RADULS_PHASES 85
 int raduls_phase_times(double* host_ms, uint32_t count);
 /* Records handled by each stage of the last sort, waiting for the device:
  * [2l] records in level l's buckets (histogram reads), [2l+1] records that
  * level moved (scatter), l = 0..19; [40] records queued for the
  * single-workgroup kernel, [41] records in tiny buckets, [42] records copied
- * back from tmp.  `count` entries are written (43 cover all). */
+ * back from tmp, [43] records through one-workgroup radix passes (a record
+ * counts once per pass), [44] records finished by wavefront jobs, [45]
+ * records finished by workgroup jobs, [46] records finished as tiny buckets.
+ * `count` entries are written (47 cover all). */
 int raduls_last_work(uint64_t* host_out, uint32_t count);
 
 /* Bytes of library workspace a sort of n records needs (beyond the caller's

@@ -341,9 +341,9 @@ raduls_tuning current_tuning(uint32_t r, uint32_t k, uint64_t n) {
 
 // Phase ids for raduls_phase_times: 0 init+seed; for level l: 1+4l prepare
 // (tile ranges, histogram reset), 2+4l histogram, 3+4l scan, 4+4l scatter;
-// then PH_ORDER, PH_SMALL, PH_COPY.
-constexpr int PH_ORDER = 1 + 4 * (int)rd::LMAX, PH_SMALL = PH_ORDER + 1, PH_COPY = PH_ORDER + 2,
-              PH_COUNT = PH_ORDER + 3;
+// then PH_ORDER, PH_SMALL (queue pass), PH_JOBS (workgroup jobs), PH_COPY.
+constexpr int PH_ORDER = 1 + 4 * (int)rd::LMAX, PH_SMALL = PH_ORDER + 1, PH_JOBS = PH_ORDER + 2,
+              PH_COPY = PH_ORDER + 3, PH_COUNT = PH_ORDER + 4;
 
 struct PhaseMarks {
   DeviceState* s;
@@ -389,6 +389,8 @@ void enqueue_sort(DeviceState& s, const Plan& p, void* records, void* tmp, const
   pm.mark(PH_ORDER);
   rd::launch_small(p, s.work, records, tmp, st);
   pm.mark(PH_SMALL);
+  rd::launch_small_jobs(p, s.work, records, tmp, st);
+  pm.mark(PH_JOBS);
   rd::launch_copy(p, s.work, records, tmp, st);
   pm.mark(PH_COPY);
   s.ph_valid = phases;
@@ -583,6 +585,7 @@ int raduls_last_work(uint64_t* host_out, uint32_t count) {
   uint64_t cr = 0;
   for (auto& b : v) cr += b.count;
   put(2 * rd::LMAX + 2, cr);
+  for (uint32_t q = 0; q < 4; q++) put(2 * rd::LMAX + 3 + q, c.stage_records[q]);
   return RADULS_OK;
 }
 

@@ -689,13 +689,16 @@ __device__ __forceinline__ void wg_finish(Ctx& c, uint64_t begin, uint32_t m, bo
 }
 
 // RADIX on a job that fits LDS: the next radix pass of the bin is made in
-// fast memory and the bins it yields, at most 32 keys each, are insertion
-// sorted (paper, Sec. 3.4-3.5).  The composites (varying key bits << ib |
-// local index) are counted by their top D <= 10 bits, placed in digit order
-// (any order within a digit), and each thread insertion-sorts the
-// sub-buckets it owns; the composites are unique, so the result is the
-// stable order.  A sub-bucket above 32 composites (a skewed job) makes the
-// workgroup finish the job by LSD from the same stage instead.
+// fast memory and the bins it yields, at most 32 keys each, are sorted
+// directly (paper, Sec. 3.4-3.5, which uses insertion sort there).  The
+// composites (varying key bits << ib | local index) are counted by their top
+// D <= 10 bits and placed in digit order (any order within a digit); then
+// each composite's final slot is its sub-bucket's start plus the number of
+// smaller composites in the sub-bucket -- the insertion sort's result,
+// computed by independent LDS reads instead of a chain of shifts.  The
+// composites are unique, so the result is the stable order.  A sub-bucket
+// above 32 composites (a skewed job) makes the workgroup finish the job by
+// LSD from the same stage instead.
 template <int RW>
 __device__ __forceinline__ void wg_radix_lds(Ctx& c, uint64_t begin, uint32_t m, bool in_tmp) {
   SmallShared& S = *c.S;
@@ -734,22 +737,25 @@ __device__ __forceinline__ void wg_radix_lds(Ctx& c, uint64_t begin, uint32_t m,
   // cnt[v] is now the end of sub-bucket v
   int big = 0;
   for (uint32_t v = threadIdx.x; v < R; v += WG) {
-    const uint32_t s0 = v ? cnt[v - 1] : 0u, e = cnt[v];
-    if (e - s0 > INSERTION_MAX) { big = 1; continue; }
-    for (uint32_t i = s0 + 1; i < e; i++) {
-      uint64_t x = c1[i];
-      uint32_t j = i;
-      while (j > s0 && c1[j - 1] > x) { c1[j] = c1[j - 1]; j--; }
-      c1[j] = x;
-    }
+    const uint32_t s0 = v ? cnt[v - 1] : 0u;
+    if (cnt[v] - s0 > INSERTION_MAX) big = 1;
   }
   if (__syncthreads_or(big)) {
     wg_sort_staged<RW>(c, begin, m, P_LSD, vary);
     return;
   }
+  for (uint32_t q = threadIdx.x; q < m; q += WG) {
+    const uint64_t x = c1[q];
+    const uint32_t v = (uint32_t)(x >> dsh);
+    const uint32_t s0 = v ? cnt[v - 1] : 0u, e = cnt[v];
+    uint32_t below = 0;
+    for (uint32_t i = s0; i < e; i++) below += c1[i] < x ? 1u : 0u;
+    c0[s0 + below] = x;
+  }
+  __syncthreads();
   const uint64_t imask = (1ull << ib) - 1;
   for (uint32_t q = threadIdx.x; q < m; q += WG)
-    store_rec<RW>(c.rec0, begin + q, lds_get<RW>(stage, (uint32_t)(c1[q] & imask)), false);
+    store_rec<RW>(c.rec0, begin + q, lds_get<RW>(stage, (uint32_t)(c0[q] & imask)), false);
   __syncthreads();
 }
 
@@ -776,6 +782,7 @@ __device__ __forceinline__ bool block_pass(Ctx& c, const Bucket& b) {
   const uint32_t KB = c.kf.kbits;
   uint32_t bit = b.bit;
   uint32_t d, R, shift;
+  if (threadIdx.x == 0) atomicAdd(&c.w.ctl->stage_records[0], (unsigned long long)m);
   Key ref = load_key<RW>(src, b.begin, c.kf);
   for (;;) {
     d = min(c.p.d_block, KB - bit);
@@ -1055,6 +1062,7 @@ __device__ __forceinline__ void run_wave_jobs(Ctx& c) {
     const uint32_t m = S.jn[i];
     const uint32_t info = S.jinfo[i];
     const uint64_t jb = base + S.jb[i];
+    if (lane_id() == 0) atomicAdd(&c.w.ctl->stage_records[1], (unsigned long long)m);
     if (m <= TINY_MAX) {
       wave_rank<RW>(c, jb, m, ctmp);
       continue;
@@ -1162,6 +1170,7 @@ __global__ __launch_bounds__(WG) void k_small(Plan p, Work w, uint8_t* rec0, uin
     uint64_t begin = x & ((1ull << 40) - 1);
     uint32_t cnt = (uint32_t)(x >> 40) & 63u;
     bool tmp = (x >> 46) & 1u;
+    if (lane_id() == 0) atomicAdd(&w.ctl->stage_records[3], (unsigned long long)cnt);
     wave_rank<RW>(c, begin, cnt, tmp);
   }
 }
@@ -1182,6 +1191,7 @@ __global__ __launch_bounds__(WG) void k_small_jobs(Plan p, Work w, uint8_t* rec0
     __syncthreads();
     if (idx >= nj) break;
     const Bucket b = w.wgjobs[idx];
+    if (threadIdx.x == 0) atomicAdd(&w.ctl->stage_records[2], (unsigned long long)b.count);
     schedule_job<RW>(c, b.begin, (uint32_t)b.count, b.bit, (b.flags & BF_TMP) != 0, b.parent);
   }
 }
@@ -1202,6 +1212,21 @@ void launch_small(const Plan& p, const Work& w, void* records, void* tmp, hipStr
 #define RD_CASE(n)                                                   \
   case n:                                                            \
     k_small<n><<<p.grid_small, WG, lds, s>>>(p, w, r0, r1);          \
+    break;
+    RD_CASE(1) RD_CASE(2) RD_CASE(3) RD_CASE(4) RD_CASE(5) RD_CASE(6) RD_CASE(7) RD_CASE(8)
+    RD_CASE(9) RD_CASE(10) RD_CASE(11) RD_CASE(12) RD_CASE(13) RD_CASE(14) RD_CASE(15) RD_CASE(16)
+#undef RD_CASE
+    default: break;
+  }
+}
+
+void launch_small_jobs(const Plan& p, const Work& w, void* records, void* tmp, hipStream_t s) {
+  uint32_t lds = small_dynamic_lds(p);
+  uint8_t* r0 = (uint8_t*)records;
+  uint8_t* r1 = (uint8_t*)tmp;
+  switch (p.rw) {
+#define RD_CASE(n)                                                   \
+  case n:                                                            \
     k_small_jobs<n><<<p.grid_small, WG, lds, s>>>(p, w, r0, r1);     \
     break;
     RD_CASE(1) RD_CASE(2) RD_CASE(3) RD_CASE(4) RD_CASE(5) RD_CASE(6) RD_CASE(7) RD_CASE(8)

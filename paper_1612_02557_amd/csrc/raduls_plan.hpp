@@ -42,6 +42,11 @@ struct Ctl {
   uint32_t error;              // bit 0: bad segment offsets, bit 1: look-back wait limit
   uint32_t overflow;           // bit 0 big list, 1 small, 2 tiny, 3 copy, 4 stack, 5 deferred jobs
   uint32_t epoch;              // look-back epoch of level 0 of this sort
+  uint32_t pad;
+  // records handled by the single-workgroup kernels: [0] one-workgroup radix
+  // passes (each pass counts its bucket), [1] wavefront jobs of the queue
+  // pass, [2] workgroup jobs of the jobs pass, [3] tiny buckets
+  unsigned long long stage_records[4];
 };
 
 struct Plan {

@@ -280,14 +280,14 @@ def set_timing(mode):
     _check(lib().raduls_set_timing(int(mode)))
 
 
-PHASES = 84
+PHASES = 85
 
 
 def phase_names(lmax: int = 20):
     names = ["setup"]
     for l in range(20):
         names += [f"L{l}.prep", f"L{l}.hist", f"L{l}.scan", f"L{l}.scatter"]
-    return names + ["order_small", "small", "copy"]
+    return names + ["order_small", "small", "small_jobs", "copy"]
 
 
 def phase_times():
@@ -298,13 +298,18 @@ def phase_times():
 
 
 def last_work():
-    """Records handled per stage by the last sort: {'levels': [(in, moved), ...], 'small', 'tiny', 'copy'}."""
-    arr = (_u64 * 43)()
-    _check(lib().raduls_last_work(arr, 43))
+    """Records handled per stage by the last sort.
+
+    {'levels': [(in, moved), ...], 'small', 'tiny', 'copy', 'block_pass',
+    'wave_jobs', 'wg_jobs', 'tiny_done'}
+    """
+    arr = (_u64 * 47)()
+    _check(lib().raduls_last_work(arr, 47))
     levels = [(arr[2 * l], arr[2 * l + 1]) for l in range(20)]
     while levels and levels[-1] == (0, 0):
         levels.pop()
-    return {"levels": levels, "small": arr[40], "tiny": arr[41], "copy": arr[42]}
+    return {"levels": levels, "small": arr[40], "tiny": arr[41], "copy": arr[42], "block_pass": arr[43],
+            "wave_jobs": arr[44], "wg_jobs": arr[45], "tiny_done": arr[46]}
 
 
 def workspace_bytes(n: int, rec_bytes: int, key_bytes: int) -> int:
