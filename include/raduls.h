@@ -95,7 +95,8 @@ typedef struct raduls_trace_row {
   uint32_t count;        /* records in the bucket */
   uint32_t observed;     /* bit p set: time_ticks[p] was measured */
   uint32_t time_ticks[3];/* elapsed 100 MHz ticks of RADIX, LSD, BITONIC */
-  uint32_t flags;        /* bit 0: counterfactual sample (every procedure timed) */
+  uint32_t flags;        /* bit 0: counterfactual sample (every feasible procedure timed);
+                            bit 1: one wavefront ran the job (RADIX not feasible there) */
 } raduls_trace_row;
 
 typedef struct raduls_stats {

@@ -69,10 +69,25 @@ def loss(theta, X, T, M, F: int, H: int, P: int) -> float:
     return float((M * d * d).sum() / s)
 
 
-def loss_and_grad(theta, X, T, M, F: int, H: int, P: int):
-    """(L, dL/dtheta) by back-propagation."""
+def loss_and_grad(theta, X, T, M, F: int, H: int, P: int, relu_gate=None):
+    """(L, dL/dtheta) by back-propagation.
+
+    ``relu_gate`` optionally fixes which hidden units count as active: a pair
+    of boolean arrays (a1 > 0, a2 > 0).  A kernel that evaluates the network
+    in float32 decides each gate in float32; comparing it against this
+    float64 reference is only meaningful with the same decisions, so a test
+    passes the float32 gates (``relu_gates_f32``) here.
+    """
     W1, b1, W2, b2, W3, b3 = unpack(theta, F, H, P)
     y, (X, a1, h1, a2, h2) = forward(theta, X, F, H, P, keep=True)
+    if relu_gate is not None:
+        g1, g2 = relu_gate
+        h1 = np.where(g1, a1, 0.0)
+        a2 = h1 @ W2.T + b2
+        h2 = np.where(g2, a2, 0.0)
+        y = h2 @ W3.T + b3
+        a1 = np.where(g1, 1.0, -1.0)
+        a2 = np.where(g2, 1.0, -1.0)
     M = np.asarray(M, dtype=np.float64)
     s = M.sum()
     if s == 0:
@@ -103,6 +118,15 @@ def adam_step(theta, g, m, v, t: int, lr: float, beta1: float = 0.9, beta2: floa
     vhat = v / (1.0 - beta2 ** t)
     theta = np.asarray(theta, dtype=np.float64) - lr * mhat / (np.sqrt(vhat) + eps)
     return theta, m, v
+
+
+def relu_gates_f32(theta, X, F: int, H: int, P: int):
+    """The (a1 > 0, a2 > 0) decisions of the network evaluated in float32."""
+    W1, b1, W2, b2, W3, b3 = (np.asarray(a, dtype=np.float32) for a in unpack(theta, F, H, P))
+    X = np.asarray(X, dtype=np.float32)
+    a1 = X @ W1.T + b1
+    a2 = np.maximum(a1, np.float32(0)) @ W2.T + b2
+    return a1 > 0, a2 > 0
 
 
 def forward_f32(theta, X, F: int, H: int, P: int):

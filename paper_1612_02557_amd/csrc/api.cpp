@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <cstddef>
 #include <map>
 #include <mutex>
 #include <string>
@@ -598,10 +599,14 @@ int raduls_sync_check(void* stream) {
   if (it == g_dev.end() || !it->second.base) return RADULS_OK;
   rd::Ctl c;
   HIPCHK(hipMemcpy(&c, it->second.work.ctl, sizeof(c), hipMemcpyDeviceToHost));
+  if (c.error == 0 && c.overflow == 0) return RADULS_OK;
+  // report once: clear the flags (the stream is idle, the copy is ordered)
+  const uint32_t zero[2] = {0, 0};
+  static_assert(offsetof(rd::Ctl, overflow) == offsetof(rd::Ctl, error) + 4, "error and overflow are adjacent");
+  HIPCHK(hipMemcpy(&it->second.work.ctl->error, zero, sizeof(zero), hipMemcpyHostToDevice));
   if (c.error & 1u) return fail(RADULS_EDEVICE, "segment offsets invalid (must start at 0, not decrease, end at total)");
   if (c.error & 2u) return fail(RADULS_EDEVICE, "look-back wait limit reached");
-  if (c.overflow) return fail(RADULS_EDEVICE, "a device queue overflowed");
-  return RADULS_OK;
+  return fail(RADULS_EDEVICE, "a device queue overflowed");
 }
 
 int raduls_set_scheduler(int mode, int forced_proc) {

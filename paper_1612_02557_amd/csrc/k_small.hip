@@ -1082,7 +1082,7 @@ __device__ __forceinline__ void run_wave_jobs(Ctx& c) {
       ticks[q] = (uint32_t)((now_ticks() - t0 + 2) / 4);  // one wave of four
     }
     if (c.w.trace && __popc(feas) > 1 && lane_id() == 0)
-      trace_row(c, m, parent, bit, proc, cf ? feas : (1u << proc), ticks, cf ? 1u : 0u);
+      trace_row(c, m, parent, bit, proc, cf ? feas : (1u << proc), ticks, (cf ? 1u : 0u) | 2u);
   }
   __syncthreads();
 }

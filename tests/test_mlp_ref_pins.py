@@ -95,3 +95,26 @@ def test_f32_forward_close_to_f64(rng):
 def test_bad_length_rejected():
     with pytest.raises(ValueError):
         M.unpack(np.zeros(10), F, H, P)
+
+
+def test_relu_gate_option():
+    """Fixed gates equal to the network's own decisions change nothing; all
+    gates closed leave only the output bias (y = b3), so every gradient but
+    db3 vanishes."""
+    rng = np.random.default_rng(11)
+    F, H, P = 9, 32, 3
+    th = rng.normal(0, 0.4, M.n_params(F, H, P))
+    X = rng.normal(size=(40, F))
+    T = rng.normal(size=(40, P))
+    Mk = (rng.random((40, P)) < 0.7).astype(float)
+    _, (_, a1, _, a2, _) = M.forward(th, X, F, H, P, keep=True)
+    L0, g0 = M.loss_and_grad(th, X, T, Mk, F, H, P)
+    L1, g1 = M.loss_and_grad(th, X, T, Mk, F, H, P, relu_gate=(a1 > 0, a2 > 0))
+    assert L0 == L1 and np.array_equal(g0, g1)
+    closed = (np.zeros_like(a1, dtype=bool), np.zeros_like(a2, dtype=bool))
+    L2, g2 = M.loss_and_grad(th, X, T, Mk, F, H, P, relu_gate=closed)
+    b3 = M.unpack(th, F, H, P)[5]
+    d = np.where(Mk > 0, b3 - T, 0.0)
+    assert L2 == pytest.approx(float((Mk * d * d).sum() / Mk.sum()))
+    assert np.all(g2[:-P] == 0.0)
+    assert np.allclose(g2[-P:], (2.0 * Mk * d / Mk.sum()).sum(axis=0))
