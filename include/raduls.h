@@ -160,6 +160,18 @@ int raduls_set_tuning(const raduls_tuning* host_tuning);
 int raduls_get_tuning(raduls_tuning* host_tuning);
 int raduls_default_tuning(uint32_t rec_bytes, uint32_t key_bytes, uint64_t n,
                           raduls_tuning* host_tuning);
+/* Autotuner (the paper picked its constants by experiment, Sec. 3.2-3.5).
+ * Times candidate tunings -- tile size, finishing-job size, resident
+ * workgroups per CU, big-bucket rule, non-temporal stores -- on two probe
+ * inputs of min(max(n_hint, 2^16), 2^25) records that it generates on the
+ * device (uniform keys; keys with 4096 distinct values; payload = index),
+ * the median of three timed sorts each, and makes the candidate with the
+ * smallest total the current tuning (raduls_get_tuning reads it).  Results
+ * are cached per (rec_bytes, key_bytes, floor(log2 n_hint)), so a second
+ * call returns at once.  Allocates and frees 4 * n * rec_bytes bytes of
+ * probe buffers (ENOMEM if that fails, the tuning then unchanged) and waits
+ * for `stream`.  No tuning changes the bytes a sort produces. */
+int raduls_tune(uint32_t rec_bytes, uint32_t key_bytes, uint64_t n_hint, void* stream);
 
 /* Record one raduls_trace_row per scheduled bucket into `rows` (device,
  * `capacity` rows); every `sample_period`-th eligible bucket (0 = none) is

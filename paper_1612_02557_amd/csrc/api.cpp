@@ -73,6 +73,7 @@ int g_sched_mode = RADULS_SCHED_HEURISTIC;
 int g_forced = 0;
 bool g_has_tuning = false;
 raduls_tuning g_tuning{};
+std::map<std::tuple<uint32_t, uint32_t, uint32_t>, raduls_tuning> g_tuned;  // autotuner results
 int g_timing = 0;  // 0 off, 1 whole sort, 2 whole sort and phases
 bool g_model_loaded = false;
 std::vector<float> g_model_host;
@@ -826,6 +827,100 @@ void raduls_release(void) {
     (void)hipSetDevice(cur);
   }
   g_dev.clear();
+}
+
+// ---- autotuner ---------------------------------------------------------------
+
+int raduls_tune(uint32_t rec_bytes, uint32_t key_bytes, uint64_t n_hint, void* stream) {
+  int rc = check_shape(rec_bytes, key_bytes);
+  if (rc) return rc;
+  const uint64_t hint = std::max<uint64_t>(n_hint, 2);
+  uint32_t cls = 0;
+  while ((2ull << cls) <= hint) cls++;
+  const auto key = std::make_tuple(rec_bytes, key_bytes, cls);
+  {
+    std::lock_guard<std::mutex> lock(g_mu);
+    auto it = g_tuned.find(key);
+    if (it != g_tuned.end()) {
+      g_tuning = it->second;
+      g_has_tuning = true;
+      return RADULS_OK;
+    }
+  }
+  const uint64_t n = std::min<uint64_t>(std::max<uint64_t>(hint, 1ull << 16), 1ull << 25);
+  const size_t bytes = (size_t)n * rec_bytes;
+  hipStream_t st = (hipStream_t)stream;
+  uint8_t* buf[4] = {nullptr, nullptr, nullptr, nullptr};  // two probes, records, tmp
+  for (auto& b : buf) {
+    if (hipMalloc(&b, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      for (auto& f : buf) if (f) hipFree(f);
+      return fail(RADULS_ENOMEM, "autotuner probe buffers");
+    }
+  }
+  rd::launch_probe_fill(buf[0], n, rec_bytes, key_bytes, 0x5EED0001ull, 0, st);
+  rd::launch_probe_fill(buf[1], n, rec_bytes, key_bytes, 0x5EED0002ull, 4096, st);
+  HIPCHK(hipGetLastError());
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  const bool had = g_has_tuning;
+  const raduls_tuning prev = g_tuning;
+  const raduls_tuning base = default_tuning(rec_bytes, key_bytes, n);
+  std::vector<raduls_tuning> cands;
+  for (uint32_t tile : {base.tile_records, base.tile_records / 2})
+    for (uint32_t job : {0u, 1024u})
+      for (uint32_t wpc : {2u, 1u})
+        for (uint32_t nt : {0u, 1u})
+          for (uint32_t rule : {0u, 1u}) {
+            raduls_tuning t = base;
+            t.tile_records = tile;
+            t.big_min = 16ull * tile;
+            t.job_records = job;
+            t.workgroups_per_cu = wpc;
+            t.nontemporal = nt;
+            t.big_rule = rule;
+            if (validate_tuning(t) == RADULS_OK) cands.push_back(t);
+          }
+  double best_ms = 1e300;
+  raduls_tuning best = base;
+  int err = RADULS_OK;
+  for (const raduls_tuning& t : cands) {
+    {
+      std::lock_guard<std::mutex> lock(g_mu);
+      g_tuning = t;
+      g_has_tuning = true;
+    }
+    double total = 0.0;
+    for (int probe = 0; probe < 2 && err == RADULS_OK; probe++) {
+      float ms[4];
+      for (int rep = 0; rep < 4 && err == RADULS_OK; rep++) {
+        if (hipMemcpyAsync(buf[2], buf[probe], bytes, hipMemcpyDeviceToDevice, st) != hipSuccess) { err = RADULS_EHIP; break; }
+        (void)hipEventRecord(e0, st);
+        err = raduls_sort(buf[2], buf[3], n, rec_bytes, key_bytes, stream);
+        (void)hipEventRecord(e1, st);
+        if (hipEventSynchronize(e1) != hipSuccess) err = RADULS_EHIP;
+        (void)hipEventElapsedTime(&ms[rep], e0, e1);
+      }
+      std::sort(ms + 1, ms + 4);  // the first run warms the workspace up
+      total += ms[2];
+    }
+    if (err != RADULS_OK) break;
+    if (total < best_ms) { best_ms = total; best = t; }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  for (auto& f : buf) hipFree(f);
+  std::lock_guard<std::mutex> lock(g_mu);
+  if (err != RADULS_OK) {
+    g_tuning = prev;
+    g_has_tuning = had;
+    return err == RADULS_EHIP ? fail(RADULS_EHIP, "autotuner run failed") : err;
+  }
+  g_tuned[key] = best;
+  g_tuning = best;
+  g_has_tuning = true;
+  return RADULS_OK;
 }
 
 // ---- scheduler-network kernels ----------------------------------------------

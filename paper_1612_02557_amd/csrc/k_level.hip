@@ -5,7 +5,7 @@
 // and a distribution traversal; Sec. 3.2-3.3: the first pass and the passes
 // on big bins use all threads).  On the GPU a level is:
 //   k_prefix   tile ranges of the list's buckets
-//   k_hist     per-bucket digit histogram (LDS, wave-aggregated) and the OR of
+//   k_hist     per-bucket digit histogram (per-wave LDS counters) and the OR of
 //              key XOR a reference key (which bits vary in the bucket)
 //   k_scan     per bucket: digit offsets, child buckets classified into the
 //              next list, the single-workgroup queue, the tiny queue or done
@@ -156,7 +156,8 @@ __global__ __launch_bounds__(WG) void k_hist(Plan p, Work w, uint32_t level, con
                                              const uint8_t* rec1) {
   constexpr uint32_t RMAX = 1u << DB;
   constexpr uint32_t HB = 16;  // keys loaded per thread before they are counted
-  __shared__ uint32_t sh[RMAX];
+  constexpr uint32_t HW = RMAX <= 256 ? NWAVES : 1;  // per-wave counters when they are small
+  __shared__ uint32_t sh[HW * RMAX];
   __shared__ uint64_t sv[2 * NWAVES];
   const Bucket* list = level_list(p, w, level);
   const uint64_t* start = level_start(p, w, level);
@@ -180,8 +181,9 @@ __global__ __launch_bounds__(WG) void k_hist(Plan p, Work w, uint32_t level, con
     uint32_t mask = (1u << d) - 1u;
     const uint8_t* src = (B.flags & BF_TMP) ? rec1 : rec0;
     Key ref = load_key<RW>(src, B.begin, kf);
-    for (uint32_t i = threadIdx.x; i < (1u << d); i += WG) sh[i] = 0;
+    for (uint32_t i = threadIdx.x; i < HW * RMAX; i += WG) sh[i] = 0;
     __syncthreads();
+    uint32_t* shw = sh + (HW > 1 ? (threadIdx.x / 64) * RMAX : 0);
     uint64_t vlo = 0, vhi = 0;
     uint64_t bend = B.begin + B.count;
     for (; t < tend; t++) {
@@ -199,11 +201,16 @@ __global__ __launch_bounds__(WG) void k_hist(Plan p, Work w, uint32_t level, con
           bool valid = j0 + u < IPT && i < bend;
           vlo |= kk[u].lo ^ ref.lo;
           vhi |= kk[u].hi ^ ref.hi;
-          uint32_t v = key_digit(kk[u], shift, mask);
-          uint64_t active = __ballot(valid);
-          uint64_t peers = match_digit(v, d, active);
-          if (valid && (uint32_t)(__ffsll((long long)peers) - 1) == lane)
-            atomicAdd(&sh[v], (uint32_t)__popcll(peers));
+          uint32_t v = key_digit(kk[u], shift, mask, kf);
+          // one LDS add per key, or one per wave when all 64 keys share the
+          // digit (runs of equal keys)
+          const uint64_t active = __ballot(valid);
+          const uint32_t v0 = __shfl(v, 0);
+          if (active == ~0ull && __ballot(v == v0) == ~0ull) {
+            if (lane == 0) atomicAdd(&shw[v0], 64u);
+          } else if (valid) {
+            atomicAdd(&shw[v], 1u);
+          }
         }
       }
     }
@@ -213,7 +220,9 @@ __global__ __launch_bounds__(WG) void k_hist(Plan p, Work w, uint32_t level, con
     __syncthreads();
     uint64_t* gh = w.hist + (uint64_t)b * RS;
     for (uint32_t i = threadIdx.x; i < (1u << d); i += WG) {
-      uint32_t c = sh[i];
+      uint32_t c = 0;
+#pragma unroll
+      for (uint32_t q = 0; q < HW; q++) c += sh[q * RMAX + i];
       if (c) atomicAdd((unsigned long long*)&gh[i], (unsigned long long)c);
     }
     if (threadIdx.x == 0) {
@@ -395,7 +404,7 @@ __global__ __launch_bounds__(WG) void k_scatter(Plan p, Work w, uint32_t level, 
       if (j < IPT) {
         uint64_t i = wbase + (uint64_t)j * 64 + lane;
         bool valid = i < bend;
-        uint32_t v = valid ? key_digit(rec_key<RW>(rec[j], kf), shift, mask) : 0u;
+        uint32_t v = valid ? key_digit(rec_key<RW>(rec[j], kf), shift, mask, kf) : 0u;
         rp[j] = rank_issue(&wcnt[wave * RMAX], v, d, valid);
         dg[j] = v;
       }
@@ -455,7 +464,7 @@ __global__ __launch_bounds__(WG) void k_scatter(Plan p, Work w, uint32_t level, 
     __syncthreads();
     for (uint32_t q = threadIdx.x; q < cnt; q += WG) {
       Rec<RW> r = lds_get<RW>(stage, q);
-      uint32_t v = key_digit(rec_key<RW>(r, kf), shift, mask);
+      uint32_t v = key_digit(rec_key<RW>(r, kf), shift, mask, kf);
       store_rec<RW>(dst, gbase[v] + q, r, nt);
     }
     __syncthreads();
@@ -521,6 +530,37 @@ __global__ void k_class_scatter(Plan p, Work w) {
 
 // ---------------------------------------------------------------------------
 // Host-side launchers.
+
+// Probe input of the autotuner: record i gets key mix(i + salt) (uniform) or
+// mix(mix(i + salt) % distinct + salt) (at most `distinct` different keys),
+// and its index as payload; other words are zero.  mix is the SplitMix64
+// output function (Steele, Lea and Flood 2014).
+__device__ __forceinline__ uint64_t probe_mix(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__global__ void k_probe_fill(uint32_t* rec, uint64_t n, uint32_t rw, uint32_t kw, uint64_t salt, uint64_t distinct) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    uint64_t h = probe_mix(i + salt);
+    if (distinct) h = probe_mix(h % distinct + salt);
+    uint32_t* r = rec + i * rw;
+    for (uint32_t w = 0; w < rw; w++) {
+      uint32_t v = 0;
+      if (w < kw) v = (uint32_t)(w & 1 ? (h >> 32) : h) ^ (w >= 2 ? (uint32_t)probe_mix(h + w) : 0u);
+      else if (w == kw) v = (uint32_t)i;
+      else if (w == kw + 1) v = (uint32_t)(i >> 32);
+      r[w] = v;
+    }
+  }
+}
+
+void launch_probe_fill(void* rec, uint64_t n, uint32_t rec_bytes, uint32_t key_bytes, uint64_t salt, uint64_t distinct,
+                       hipStream_t s) {
+  uint32_t grid = (uint32_t)std::min<uint64_t>((n + WG - 1) / WG, 65536);
+  if (grid == 0) return;
+  k_probe_fill<<<grid, WG, 0, s>>>((uint32_t*)rec, n, rec_bytes / 4, (key_bytes + 3) / 4, salt, distinct);
+}
 
 void launch_init(const Work& w, hipStream_t s) {
   k_init<<<1, WG, 0, s>>>(w);

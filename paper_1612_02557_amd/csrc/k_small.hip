@@ -639,7 +639,7 @@ __device__ __forceinline__ void wg_sort_staged(Ctx& c, uint64_t begin, uint32_t 
         uint32_t q = wave * PW + j * 64 + lane;
         bool valid = q < m;
         uint32_t idx = valid ? perm0[q] : 0u;
-        uint32_t v = valid ? key_digit(lds_key<RW>(stage, idx, c.kf), s, R - 1) : 0u;
+        uint32_t v = valid ? key_digit(lds_key<RW>(stage, idx, c.kf), s, R - 1, c.kf) : 0u;
         rp[j] = rank_issue(&S.wcnt[wave * RB], v, d, valid);
         dg[j] = v;
         ix[j] = idx;
@@ -804,7 +804,7 @@ __device__ __forceinline__ bool block_pass(Ctx& c, const Bucket& b) {
         bool valid = q < m;
         vlo |= kk[u].lo ^ ref.lo;
         vhi |= kk[u].hi ^ ref.hi;
-        uint32_t v = key_digit(kk[u], shift, R - 1);
+        uint32_t v = key_digit(kk[u], shift, R - 1, c.kf);
         uint64_t active = __ballot(valid);
         uint64_t peers = match_digit(v, d, active);
         if (valid && (uint32_t)(__ffsll((long long)peers) - 1) == lane) atomicAdd(&S.hist[v], (uint32_t)__popcll(peers));
@@ -865,7 +865,7 @@ __device__ __forceinline__ bool block_pass(Ctx& c, const Bucket& b) {
       if (j < IPT) {
         uint32_t q = wb + j * 64 + lane;
         bool valid = q < m;
-        uint32_t v = valid ? key_digit(rec_key<RW>(rec[j], c.kf), shift, R - 1) : 0u;
+        uint32_t v = valid ? key_digit(rec_key<RW>(rec[j], c.kf), shift, R - 1, c.kf) : 0u;
         rp[j] = rank_issue(&S.wcnt[wave * RB], v, d, valid);
         dg[j] = v;
       }
@@ -882,7 +882,7 @@ __device__ __forceinline__ bool block_pass(Ctx& c, const Bucket& b) {
     __syncthreads();
     for (uint32_t q = threadIdx.x; q < cnt; q += WG) {
       Rec<RW> r = lds_get<RW>(c.dyn, q);
-      uint32_t v = key_digit(rec_key<RW>(r, c.kf), shift, R - 1);
+      uint32_t v = key_digit(rec_key<RW>(r, c.kf), shift, R - 1, c.kf);
       store_rec<RW>(dst, b.begin + S.run[v] + (q - S.toff[v]), r, false);
     }
     __syncthreads();
@@ -941,15 +941,17 @@ __device__ __forceinline__ void schedule_job(Ctx& c, uint64_t begin, uint32_t m,
   const bool cf = sample_job(c, feas);
   const uint32_t runs = cf ? 3u : 1u;
   uint32_t ticks[3] = {0, 0, 0};
+  // a sample first runs the chosen procedure untimed, so that every timed
+  // run finds the job's records in cache alike
 #pragma unroll 1
-  for (uint32_t k = 1; k <= runs; k++) {
+  for (uint32_t k = cf ? 0u : 1u; k <= runs; k++) {
     const uint32_t q = cf ? (proc + k) % 3 : proc;
     if (!((feas >> q) & 1u) && cf) continue;
     __syncthreads();
     uint64_t t0 = now_ticks();
     run_job<RW>(c, q, begin, m, in_tmp);
     __syncthreads();
-    ticks[q] = (uint32_t)(now_ticks() - t0);
+    if (k > 0) ticks[q] = (uint32_t)(now_ticks() - t0);
   }
   if (c.w.trace && __popc(feas) > 1 && threadIdx.x == 0)
     trace_row(c, m, parent, bit, proc, cf ? feas : (1u << proc), ticks, cf ? 1u : 0u);
@@ -1073,13 +1075,13 @@ __device__ __forceinline__ void run_wave_jobs(Ctx& c) {
     const uint32_t runs = cf ? 3u : 1u;
     const bool narrow = (c.kf.kbits - bit) + (32 - __clz(m - 1)) <= 64;
 #pragma unroll 1
-    for (uint32_t k = 1; k <= runs; k++) {
+    for (uint32_t k = cf ? 0u : 1u; k <= runs; k++) {  // k = 0: untimed warm-up of a sample
       const uint32_t q = cf ? (proc + k) % 3 : proc;
       if (cf && !((feas >> q) & 1u)) continue;
       uint64_t t0 = now_ticks();
       if (narrow) wave_sort64<RW>(c, jb, m, ctmp, q, reg);
       else wave_sort<RW>(c, jb, m, ctmp, q, reg);
-      ticks[q] = (uint32_t)((now_ticks() - t0 + 2) / 4);  // one wave of four
+      if (k > 0) ticks[q] = (uint32_t)((now_ticks() - t0 + 2) / 4);  // one wave of four
     }
     if (c.w.trace && __popc(feas) > 1 && lane_id() == 0)
       trace_row(c, m, parent, bit, proc, cf ? feas : (1u << proc), ticks, (cf ? 1u : 0u) | 2u);

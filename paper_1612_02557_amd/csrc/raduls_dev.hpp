@@ -181,8 +181,10 @@ __device__ __forceinline__ uint64_t shr128_lo(Key k, uint32_t s) {
   return (k.lo >> s) | (k.hi << (64 - s));
 }
 
-// Digit of width d whose lowest bit is `shift` (d <= 16).
-__device__ __forceinline__ uint32_t key_digit(Key k, uint32_t shift, uint32_t mask) {
+// Digit of width d whose lowest bit is `shift` (d <= 16).  Keys of at most
+// 64 bits (the key format is the same for the whole launch) need one shift.
+__device__ __forceinline__ uint32_t key_digit(Key k, uint32_t shift, uint32_t mask, const KeyFmt& f) {
+  if (f.kbits <= 64) return (uint32_t)(k.lo >> shift) & mask;
   return (uint32_t)shr128_lo(k, shift) & mask;
 }
 
@@ -209,12 +211,25 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
   return l == 0 ? 0ull : (~0ull >> (64 - l));
 }
 
-// Lanes of the wave (among `active`) holding the same digit value v (d bits).
+// Lanes of the wave (among `active`) holding the same digit value v (d bits):
+// per bit, the lanes whose bit agrees with this lane's (the ballot, or its
+// complement where this lane's bit is 0: ballot XOR (bit - 1)).
+template <uint32_t D>
+__device__ __forceinline__ uint64_t match_digit_n(uint32_t v, uint64_t active) {
+  uint64_t peers = active;
+#pragma unroll
+  for (uint32_t b = 0; b < D; b++) {
+    const uint32_t bit = (v >> b) & 1u;
+    peers &= __ballot(bit) ^ ((uint64_t)bit - 1ull);
+  }
+  return peers;
+}
 __device__ __forceinline__ uint64_t match_digit(uint32_t v, uint32_t d, uint64_t active) {
+  if (d == 8) return match_digit_n<8>(v, active);
   uint64_t peers = active;
   for (uint32_t b = 0; b < d; b++) {
-    uint64_t bal = __ballot((v >> b) & 1u);
-    peers &= ((v >> b) & 1u) ? bal : ~bal;
+    const uint32_t bit = (v >> b) & 1u;
+    peers &= __ballot(bit) ^ ((uint64_t)bit - 1ull);
   }
   return peers;
 }

@@ -7,6 +7,8 @@
 namespace rd {
 
 void launch_init(const Work& w, hipStream_t s);
+void launch_probe_fill(void* rec, uint64_t n, uint32_t rec_bytes, uint32_t key_bytes, uint64_t salt, uint64_t distinct,
+                       hipStream_t s);
 void launch_seed_single(const Plan& p, const Work& w, hipStream_t s);
 void launch_seed_segments(const Plan& p, const Work& w, const uint64_t* off, uint32_t S, hipStream_t s);
 void launch_level_prep(const Plan& p, const Work& w, uint32_t level, hipStream_t s);

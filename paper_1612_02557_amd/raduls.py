@@ -72,6 +72,7 @@ TRACE_ROW_BYTES = ctypes.sizeof(TraceRow)
 
 _SIGS = {
     "raduls_sort": (_i32, [_vp, _vp, _u64, _u32, _u32, _vp]),
+    "raduls_tune": (_i32, [_u32, _u32, _u64, _vp]),
     "raduls_sort_segmented": (_i32, [_vp, _vp, _vp, _u32, _u64, _u32, _u32, _vp]),
     "raduls_partition": (_i32, [_vp, _vp, _u64, _u32, _u32, _u32, _u32, _vp, _vp]),
     "raduls_sync_check": (_i32, [_vp]),
@@ -114,6 +115,9 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+        # Device memory and streams come from PyTorch, so the library must bind
+        # to the HIP runtime PyTorch loads: load that one first.
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             f = getattr(L, name)
@@ -246,6 +250,12 @@ def default_tuning(rec_bytes: int, key_bytes: int, n: int) -> Tuning:
 
 def set_tuning(t: Tuning | None):
     _check(lib().raduls_set_tuning(ctypes.byref(t) if t is not None else None))
+
+
+def tune(rec_bytes: int, key_bytes: int, n_hint: int, stream=None) -> Tuning:
+    """Run the library's autotuner; returns the tuning it made current."""
+    _check(lib().raduls_tune(rec_bytes, key_bytes, n_hint, _stream(stream)))
+    return get_tuning()
 
 
 def get_tuning() -> Tuning | None:

@@ -3,6 +3,7 @@
 // pure function of (stream bases, global index), so any range regenerates
 // on its own and matches the host generator byte for byte.
 #include <hip/hip_runtime.h>
+#include <cstdio>
 #include <stdint.h>
 
 namespace {
@@ -78,7 +79,14 @@ extern "C" int synth_fill(void* out, uint64_t i0, uint64_t count, uint32_t rec_b
   for (int w = 0; w < 16; w++) B.payload[w] = bases[6 + w];
   B.p24 = bases[22];
   uint64_t blocks = (count + 255) / 256;
+  if (blocks > 0x7FFFFFFFull) return -2;
+  (void)hipGetLastError();  // report this launch's status only
   hipLaunchKernelGGL(k_fill, dim3((uint32_t)blocks), dim3(256), 0, (hipStream_t)stream, (uint32_t*)out, i0, count,
                      rec_bytes, key_bytes, dist, payload_index, B, cdf, m);
-  return hipGetLastError() == hipSuccess ? 0 : -3;
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    fprintf(stderr, "synth_fill: %s\n", hipGetErrorString(e));
+    return -3;
+  }
+  return 0;
 }

@@ -33,6 +33,7 @@ def lib():
     if _lib is None:
         if not os.path.exists(SO):
             raise RuntimeError(f"{SO} is not built")
+        import torch  # noqa: F401  (bind to the HIP runtime PyTorch loads)
         L = ctypes.CDLL(SO)
         v = ctypes.c_void_p
         L.synth_fill.argtypes = [v, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int,

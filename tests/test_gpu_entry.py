@@ -366,3 +366,29 @@ def test_model_blob_validation(R):
     zero_scale = R.model_blob(theta, mean, np.zeros(F))
     assert R.load_model_raw(zero_scale) == R.EMODEL
     R.unload_model()
+
+
+# ---------------------------------------------------------------------------
+# autotuner
+
+def test_autotuner_picks_a_valid_tuning(R):
+    import time
+    note("autotuner r=16 k=8 n_hint=2^22")
+    t0 = time.perf_counter()
+    t = R.tune(16, 8, 1 << 22)
+    first = time.perf_counter() - t0
+    try:
+        assert t is not None
+        d = t.as_dict()
+        assert d["tile_records"] in (2048, 4096) and d["workgroups_per_cu"] in (1, 2)
+        t0 = time.perf_counter()
+        assert R.tune(16, 8, (1 << 22) + 5).as_dict() == d     # same size class: cached
+        assert time.perf_counter() - t0 < first
+        for dist in ("uniform", "zipf"):
+            host = synth.generate(synth.Spec(n=1 << 21, dist=dist, seed=31))
+            dev = to_dev(host)
+            R.sort(dev, 8)
+            R.sync_check()
+            assert np.array_equal(dev.cpu().numpy(), oracle.sort(host, 8)), dist
+    finally:
+        R.set_tuning(None)

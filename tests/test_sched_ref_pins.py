@@ -63,3 +63,16 @@ def test_features_shape_and_values():
     assert len(f) == 9
     assert f[0] == 10 and f[1] == 16 and f[2] == 6 and f[8] == 1.0
     assert f[3] == 48 / 64 and f[4] == 16 / 64 and f[7] == 14 - 16 + 0.0
+
+
+def test_learn_regret_matches_reference():
+    """The training module's vectorised regret equals the reference definition."""
+    import numpy as np
+    from paper_1612_02557_amd import learn
+    rng = np.random.default_rng(5)
+    n = 200
+    feas = rng.integers(1, 8, n).astype(np.uint32)
+    ticks = rng.integers(1, 10_000, (n, 3)).astype(np.uint32)
+    chosen = np.array([rng.choice([q for q in range(3) if (f >> q) & 1]) for f in feas])
+    times = [[float(ticks[i, q]) if (feas[i] >> q) & 1 else None for q in range(3)] for i in range(n)]
+    assert learn.regret(chosen, ticks, feas) == pytest.approx(S.regret(list(chosen), times))
