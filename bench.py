@@ -107,6 +107,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-sample-log2", type=int, default=26)
     ap.add_argument("--phases", type=int, default=1, help="1: per-phase events during the timed steps")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-scheduler leg")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -234,6 +235,27 @@ def main():
         "timed_wall_s": wall,
         "verified": verified,
     }
+    # learned scheduler on the same input (the committed trained network)
+    learned = None
+    model = os.path.join(ROOT, "paper_1612_02557_amd", "models", "sched_mlp.rdls")
+    if not args.no_learned and os.path.exists(model):
+        with open(model, "rb") as f:
+            raduls.load_model(f.read())
+        raduls.set_scheduler(raduls.SCHED_LEARNED)
+        raduls.set_timing(1)
+        step()
+        lt = [step() for _ in range(args.steps)]
+        lok = None
+        if r == 16 and k == 8:
+            lok = exact_index_check(rec, pristine) is None
+        raduls.set_scheduler(raduls.SCHED_HEURISTIC)
+        raduls.unload_model()
+        lms = statistics.mean(lt)
+        learned = {"ms_per_step": lms, "value": n / (lms / 1e3), "unit": "records/s",
+                   "plain_over_learned": ms_per_step / lms, "verified": lok,
+                   "model": "paper_1612_02557_amd/models/sched_mlp.rdls"}
+        log(f"learned scheduler: {lms:.3f} ms per step")
+    out["learned"] = learned
     del tmp, rec
     torch.cuda.empty_cache()
     if not args.no_cpu:

@@ -926,8 +926,8 @@ int raduls_tune(uint32_t rec_bytes, uint32_t key_bytes, uint64_t n_hint, void* s
 // ---- scheduler-network kernels ----------------------------------------------
 
 int raduls_mlp_forward(const float* X, const float* theta, float* Y, uint32_t batch, void* stream) {
-  if (!X || !theta || !Y) return fail(RADULS_EINVAL, "null pointer");
   if (batch == 0) return RADULS_OK;
+  if (!X || !theta || !Y) return fail(RADULS_EINVAL, "null pointer");
   rd::launch_mlp_forward(X, theta, Y, batch, (hipStream_t)stream);
   HIPCHK(hipGetLastError());
   return RADULS_OK;

@@ -697,8 +697,10 @@ __device__ __forceinline__ void wg_finish(Ctx& c, uint64_t begin, uint32_t m, bo
 // smaller composites in the sub-bucket -- the insertion sort's result,
 // computed by independent LDS reads instead of a chain of shifts.  The
 // composites are unique, so the result is the stable order.  A sub-bucket
-// above 32 composites (a skewed job) makes the workgroup finish the job by
-// LSD from the same stage instead.
+// above 32 composites (a skewed job: runs of equal keys) makes the workgroup
+// finish the job from the same stage by the bitonic network instead (by LSD
+// if the job exceeds the bitonic capacity), which costs the same whatever
+// the duplicates.
 template <int RW>
 __device__ __forceinline__ void wg_radix_lds(Ctx& c, uint64_t begin, uint32_t m, bool in_tmp) {
   SmallShared& S = *c.S;
@@ -741,7 +743,7 @@ __device__ __forceinline__ void wg_radix_lds(Ctx& c, uint64_t begin, uint32_t m,
     if (cnt[v] - s0 > INSERTION_MAX) big = 1;
   }
   if (__syncthreads_or(big)) {
-    wg_sort_staged<RW>(c, begin, m, P_LSD, vary);
+    wg_sort_staged<RW>(c, begin, m, m <= c.p.bitonic_max ? P_BITONIC : P_LSD, vary);
     return;
   }
   for (uint32_t q = threadIdx.x; q < m; q += WG) {
@@ -937,19 +939,40 @@ __device__ __forceinline__ void schedule_job(Ctx& c, uint64_t begin, uint32_t m,
                                              uint64_t parent) {
   const uint32_t KB = c.kf.kbits;
   const uint32_t feas = feasible_mask(c.p, m, bit, KB, true);
-  const uint32_t proc = choose_proc(c.p, c.w.model, m, parent, bit, KB, feas);
+  uint32_t proc;
+  if (c.p.sched_mode == RADULS_SCHED_LEARNED && c.w.model && __popc(feas) > 1) {
+    // the network is evaluated by one wavefront and its choice shared
+    SmallShared& S = *c.S;
+    if (threadIdx.x < 64) {
+      const uint32_t pr = choose_proc_wave(c.p, c.w.model, m, parent, bit, KB, feas);
+      if (threadIdx.x == 0) S.bcast = pr;
+    }
+    __syncthreads();
+    proc = S.bcast;
+    __syncthreads();
+  } else {
+    proc = choose_proc(c.p, c.w.model, m, parent, bit, KB, feas);
+  }
   const bool cf = sample_job(c, feas);
   const uint32_t runs = cf ? 3u : 1u;
   uint32_t ticks[3] = {0, 0, 0};
-  // a sample first runs the chosen procedure untimed, so that every timed
-  // run finds the job's records in cache alike
+  // A sample keeps its input: a job that lies in records is first copied to
+  // the same place in tmp, and every run then reads tmp and writes records,
+  // so each procedure sees the same unsorted input.  It also first runs the
+  // chosen procedure untimed, so every timed run finds the records in cache
+  // alike.
+  bool src_tmp = in_tmp;
+  if (cf && !in_tmp) {
+    for (uint32_t q = threadIdx.x; q < m; q += WG) store_rec<RW>(c.rec1, begin + q, load_rec<RW>(c.rec0, begin + q), false);
+    src_tmp = true;
+  }
 #pragma unroll 1
   for (uint32_t k = cf ? 0u : 1u; k <= runs; k++) {
     const uint32_t q = cf ? (proc + k) % 3 : proc;
     if (!((feas >> q) & 1u) && cf) continue;
     __syncthreads();
     uint64_t t0 = now_ticks();
-    run_job<RW>(c, q, begin, m, in_tmp);
+    run_job<RW>(c, q, begin, m, src_tmp);
     __syncthreads();
     if (k > 0) ticks[q] = (uint32_t)(now_ticks() - t0);
   }
@@ -1074,13 +1097,20 @@ __device__ __forceinline__ void run_wave_jobs(Ctx& c) {
     uint32_t ticks[3] = {0, 0, 0};
     const uint32_t runs = cf ? 3u : 1u;
     const bool narrow = (c.kf.kbits - bit) + (32 - __clz(m - 1)) <= 64;
+    // a sample keeps its input in tmp (see schedule_job)
+    bool src_tmp = ctmp;
+    if (cf && !ctmp) {
+      for (uint32_t q = lane_id(); q < m; q += 64) store_rec<RW>(c.rec1, jb + q, load_rec<RW>(c.rec0, jb + q), false);
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+      src_tmp = true;
+    }
 #pragma unroll 1
     for (uint32_t k = cf ? 0u : 1u; k <= runs; k++) {  // k = 0: untimed warm-up of a sample
       const uint32_t q = cf ? (proc + k) % 3 : proc;
       if (cf && !((feas >> q) & 1u)) continue;
       uint64_t t0 = now_ticks();
-      if (narrow) wave_sort64<RW>(c, jb, m, ctmp, q, reg);
-      else wave_sort<RW>(c, jb, m, ctmp, q, reg);
+      if (narrow) wave_sort64<RW>(c, jb, m, src_tmp, q, reg);
+      else wave_sort<RW>(c, jb, m, src_tmp, q, reg);
       if (k > 0) ticks[q] = (uint32_t)((now_ticks() - t0 + 2) / 4);  // one wave of four
     }
     if (c.w.trace && __popc(feas) > 1 && lane_id() == 0)

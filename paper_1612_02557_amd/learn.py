@@ -38,11 +38,15 @@ ROW = np.dtype([("features", "<f4", (9,)), ("chosen", "<u4"), ("count", "<u4"), 
                 ("ticks", "<u4", (3,)), ("flags", "<u4")])
 MODEL_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "models", "sched_mlp.rdls")
 
-# (log2 n, rec_bytes, key_bytes, distribution) of the training workloads
-TRAIN = [(24, 16, 8, d) for d in ("uniform", "zipf", "prefix", "mix")] + \
-        [(26, 16, 8, d) for d in ("uniform", "zipf", "mix")] + \
-        [(24, 8, 8, "mix"), (24, 32, 8, "mix"), (24, 32, 16, "mix"), (23, 16, 16, "zipf")]
-HOLDOUT = [(25, 16, 8, d) for d in ("uniform", "zipf", "prefix", "mix")]
+# (log2 n, rec_bytes, key_bytes, distribution) of the training workloads:
+# every size class from 2^22 to 2^27 (each gives a different job structure:
+# queued buckets, one-workgroup passes, runs of small children) for each key
+# distribution, and other record shapes.  Held out: new data (other seeds)
+# of the same shapes.
+DISTS = ("uniform", "zipf", "prefix", "mix")
+TRAIN = [(lg, 16, 8, d) for lg in range(22, 28) for d in DISTS] + \
+        [(lg, r, k, d) for lg in (23, 25) for (r, k) in ((8, 8), (32, 8), (32, 16)) for d in ("uniform", "zipf")]
+HOLDOUT = [(lg, 16, 8, d) for lg in (23, 25, 27) for d in DISTS] + [(24, 32, 16, "zipf"), (24, 8, 8, "mix")]
 
 
 def log(msg):
@@ -55,7 +59,7 @@ def _inputs(lg, r, k, dist, seed):
     return sdev.generate(synth.Spec(n=1 << lg, rec_bytes=r, key_bytes=k, dist=dist, payload="index", seed=seed))
 
 
-def collect(workloads, sample_period=3, seed=100, cap=1 << 21):
+def collect(workloads, sample_period=3, seed=100, cap=1 << 21, per_workload=None):
     """Trace rows (numpy structured array) of sorting each workload once."""
     import torch
     out = []
@@ -71,6 +75,8 @@ def collect(workloads, sample_period=3, seed=100, cap=1 << 21):
         tr = np.frombuffer(rows[: min(cnt, cap) * ROW.itemsize].cpu().numpy().tobytes(), dtype=ROW).copy()
         log(f"traced 2^{lg} x {r} B k={k} {dist}: {len(tr)} rows, {int(((tr['flags'] & 1) != 0).sum())} sampled")
         out.append(tr)
+        if per_workload is not None:
+            per_workload.append(((lg, r, k, dist), tr))
         del data, tmp
     return np.concatenate(out) if out else np.zeros(0, dtype=ROW)
 
@@ -153,6 +159,8 @@ def regret(chosen, times, feas):
 def evaluate(theta, mean, scale, tr):
     """Regret of the learned and of the recorded (running) choices on sampled rows."""
     s = tr[(tr["flags"] & 1) != 0]
+    if len(s) == 0:
+        return {"rows": 0}
     feas = s["observed"].astype(np.uint32)
     Y = predict(theta, mean, scale, s["features"].astype(np.float32))
     learned = masked_argmin(Y, feas)
@@ -199,7 +207,7 @@ def compare(blob, configs, reps=5, seed=500):
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", required=True)
-    ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--steps", type=int, default=6000)
     ap.add_argument("--period", type=int, default=3)
     ap.add_argument("--compare-log2n", type=int, default=27)
     args = ap.parse_args(argv)
@@ -209,7 +217,8 @@ def main(argv=None):
     raduls.unload_model()
     t0 = time.time()
     tr = collect(TRAIN, args.period, seed=100)
-    ho = collect(HOLDOUT, args.period, seed=300)
+    ho_parts = []
+    ho = collect(HOLDOUT, args.period, seed=300, per_workload=ho_parts)
     X, T, M = dataset(tr)
     log(f"{len(tr)} training rows, {len(ho)} held-out rows; training")
     theta, mean, scale, hist = train(X, T, M, steps=args.steps)
@@ -218,12 +227,23 @@ def main(argv=None):
         f.write(blob)
     ev_train = evaluate(theta, mean, scale, tr)
     ev_hold = evaluate(theta, mean, scale, ho)
+    per = []
+    for (w, part) in ho_parts:
+        e = evaluate(theta, mean, scale, part)
+        s_ = part[(part["flags"] & 1) != 0]
+        mean_ticks = []
+        for q in range(P):
+            sel = ((s_["observed"] >> q) & 1) != 0
+            mean_ticks.append(float(s_["ticks"][sel, q].mean()) if sel.any() else None)
+        e.update({"workload": list(w), "mean_ticks_per_proc": mean_ticks,
+                  "median_job_records": float(np.median(s_["count"])) if len(s_) else None})
+        per.append(e)
     log(f"held-out regret: learned {ev_hold['regret_learned']:.4f}, heuristic {ev_hold['regret_heuristic']:.4f}")
     lg = args.compare_log2n
     cmp_ = compare(blob, [(lg, 16, 8, d) for d in ("uniform", "zipf", "prefix", "mix")] +
                    [(lg - 1, 32, 16, "zipf"), (lg, 8, 8, "mix")])
     report = {"train_rows": int(len(tr)), "holdout_rows": int(len(ho)), "loss_history": hist,
-              "train_eval": ev_train, "holdout_eval": ev_hold, "end_to_end": cmp_,
+              "train_eval": ev_train, "holdout_eval": ev_hold, "holdout_per_workload": per, "end_to_end": cmp_,
               "train_workloads": [list(w) for w in TRAIN], "holdout_workloads": [list(w) for w in HOLDOUT],
               "seconds": time.time() - t0}
     with open(os.path.join(args.out, "learn_report.json"), "w") as f:

@@ -120,6 +120,7 @@ def test_status_strings_and_workspace(R):
 def test_mlp_entry_validation(R):
     L = R.lib()
     assert L.raduls_mlp_forward(None, None, None, 4, None) == R.EINVAL
+    assert L.raduls_mlp_forward(None, None, None, 0, None) == R.OK
     assert L.raduls_mlp_adam(1 << 20, 1 << 21, 1 << 22, 1 << 23, 0, ctypes.c_float(1e-3), ctypes.c_float(0.9),
                              ctypes.c_float(0.999), ctypes.c_float(1e-8), None) == R.EINVAL   # t counts from 1
 
