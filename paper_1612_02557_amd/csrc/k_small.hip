@@ -430,24 +430,10 @@ __device__ __forceinline__ void wave_sort64(Ctx& c, uint64_t begin, uint32_t m, 
 // ---------------------------------------------------------------------------
 // Workgroup procedures.
 
-// Load m records into the LDS stage and reduce the varying-bit mask.
+// OR over the staged records of (key XOR the first key): the bits that vary.
 template <int RW>
-__device__ __forceinline__ Key wg_stage(Ctx& c, uint64_t begin, uint32_t m, bool in_tmp) {
-  const uint8_t* src = in_tmp ? c.rec1 : c.rec0;
+__device__ __forceinline__ Key stage_vary(Ctx& c, uint32_t m) {
   SmallShared& S = *c.S;
-  for (uint32_t q0 = 0; q0 < m; q0 += WG * 8) {
-    Rec<RW> r[8];
-#pragma unroll
-    for (int u = 0; u < 8; u++) {
-      uint32_t q = q0 + u * WG + threadIdx.x;
-      if (q < m) r[u] = load_rec<RW>(src, begin + q);
-    }
-#pragma unroll
-    for (int u = 0; u < 8; u++) {
-      uint32_t q = q0 + u * WG + threadIdx.x;
-      if (q < m) lds_put<RW>(c.dyn, q, r[u]);
-    }
-  }
   __syncthreads();
   Key ref = lds_key<RW>(c.dyn, 0, c.kf);
   uint64_t vlo = 0, vhi = 0;
@@ -465,6 +451,55 @@ __device__ __forceinline__ Key wg_stage(Ctx& c, uint64_t begin, uint32_t m, bool
   for (int q = 0; q < NWAVES; q++) { v.lo |= S.vary[2 * q]; v.hi |= S.vary[2 * q + 1]; }
   __syncthreads();
   return v;
+}
+
+// A job's records held in registers (record q = u * WG + thread in slot u),
+// so the next job's loads can be in flight while this one is sorted.
+template <int RW>
+struct JobRegs {
+  static constexpr uint32_t CMAX0 = (60u * 1024u / (4u * RW + 16u)) / 64u * 64u;
+  static constexpr uint32_t CMAX = CMAX0 < 4096u ? CMAX0 : 4096u;  // the largest LDS job
+  static constexpr uint32_t N = (CMAX + WG - 1) / WG;
+  Rec<RW> r[N];
+};
+
+template <int RW>
+__device__ __forceinline__ void regs_load(Ctx& c, JobRegs<RW>& jr, uint64_t begin, uint32_t m, bool in_tmp) {
+  const uint8_t* src = in_tmp ? c.rec1 : c.rec0;
+#pragma unroll
+  for (uint32_t u = 0; u < JobRegs<RW>::N; u++) {
+    uint32_t q = u * WG + threadIdx.x;
+    if (q < m) jr.r[u] = load_rec<RW>(src, begin + q);
+  }
+}
+
+template <int RW>
+__device__ __forceinline__ void regs_stage(Ctx& c, const JobRegs<RW>& jr, uint32_t m) {
+#pragma unroll
+  for (uint32_t u = 0; u < JobRegs<RW>::N; u++) {
+    uint32_t q = u * WG + threadIdx.x;
+    if (q < m) lds_put<RW>(c.dyn, q, jr.r[u]);
+  }
+}
+
+// Load m records into the LDS stage and reduce the varying-bit mask.
+template <int RW>
+__device__ __forceinline__ Key wg_stage(Ctx& c, uint64_t begin, uint32_t m, bool in_tmp) {
+  const uint8_t* src = in_tmp ? c.rec1 : c.rec0;
+  for (uint32_t q0 = 0; q0 < m; q0 += WG * 8) {
+    Rec<RW> r[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+      uint32_t q = q0 + u * WG + threadIdx.x;
+      if (q < m) r[u] = load_rec<RW>(src, begin + q);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+      uint32_t q = q0 + u * WG + threadIdx.x;
+      if (q < m) lds_put<RW>(c.dyn, q, r[u]);
+    }
+  }
+  return stage_vary<RW>(c, m);
 }
 
 // Per-digit wave offsets and tile offsets after ranking: wcnt[q][v] becomes
@@ -663,16 +698,17 @@ __device__ __forceinline__ void wg_sort_staged(Ctx& c, uint64_t begin, uint32_t 
   __syncthreads();
 }
 
-// Stage a job; returns false when it is finished already (at most one
-// record, or every key equal), after putting it in records if it lay in tmp.
+// Stage a job (unless `staged`: its records are in the LDS stage already);
+// returns false when it is finished already (at most one record, or every
+// key equal), after putting it in records if it lay in tmp.
 template <int RW>
-__device__ __forceinline__ bool wg_begin(Ctx& c, uint64_t begin, uint32_t m, bool in_tmp, Key& vary) {
+__device__ __forceinline__ bool wg_begin(Ctx& c, uint64_t begin, uint32_t m, bool in_tmp, Key& vary, bool staged) {
   if (m <= 1) {
     if (m == 1 && in_tmp && threadIdx.x == 0) store_rec<RW>(c.rec0, begin, load_rec<RW>(c.rec1, begin), false);
     __syncthreads();
     return false;
   }
-  vary = wg_stage<RW>(c, begin, m, in_tmp);
+  vary = staged ? stage_vary<RW>(c, m) : wg_stage<RW>(c, begin, m, in_tmp);
   if (vary.lo == 0 && vary.hi == 0) {
     if (in_tmp)
       for (uint32_t q = threadIdx.x; q < m; q += WG) store_rec<RW>(c.rec0, begin + q, lds_get<RW>(c.dyn, q), false);
@@ -683,9 +719,10 @@ __device__ __forceinline__ bool wg_begin(Ctx& c, uint64_t begin, uint32_t m, boo
 }
 
 template <int RW>
-__device__ __forceinline__ void wg_finish(Ctx& c, uint64_t begin, uint32_t m, bool in_tmp, uint32_t proc) {
+__device__ __forceinline__ void wg_finish(Ctx& c, uint64_t begin, uint32_t m, bool in_tmp, uint32_t proc,
+                                          bool staged = false) {
   Key vary;
-  if (wg_begin<RW>(c, begin, m, in_tmp, vary)) wg_sort_staged<RW>(c, begin, m, proc, vary);
+  if (wg_begin<RW>(c, begin, m, in_tmp, vary, staged)) wg_sort_staged<RW>(c, begin, m, proc, vary);
 }
 
 // RADIX on a job that fits LDS: the next radix pass of the bin is made in
@@ -702,10 +739,10 @@ __device__ __forceinline__ void wg_finish(Ctx& c, uint64_t begin, uint32_t m, bo
 // if the job exceeds the bitonic capacity), which costs the same whatever
 // the duplicates.
 template <int RW>
-__device__ __forceinline__ void wg_radix_lds(Ctx& c, uint64_t begin, uint32_t m, bool in_tmp) {
+__device__ __forceinline__ void wg_radix_lds(Ctx& c, uint64_t begin, uint32_t m, bool in_tmp, bool staged) {
   SmallShared& S = *c.S;
   Key vary;
-  if (!wg_begin<RW>(c, begin, m, in_tmp, vary)) return;
+  if (!wg_begin<RW>(c, begin, m, in_tmp, vary, staged)) return;
   const uint32_t lo = ctz128(vary);
   const uint32_t W = bitlen128(vary) - lo;
   const uint32_t ib = 32 - __clz(m - 1);
@@ -912,7 +949,7 @@ __device__ __forceinline__ void trace_row(Ctx& c, uint64_t m, uint64_t parent, u
 }
 
 template <int RW>
-__device__ __forceinline__ void run_job(Ctx& c, uint32_t proc, uint64_t begin, uint32_t m, bool in_tmp);
+__device__ __forceinline__ void run_job(Ctx& c, uint32_t proc, uint64_t begin, uint32_t m, bool in_tmp, bool staged);
 
 // Is this job sampled for counterfactual timing?  (Workgroup-uniform.)
 __device__ __forceinline__ bool sample_job(Ctx& c, uint32_t feas) {
@@ -936,7 +973,8 @@ __device__ __forceinline__ bool sample_job(Ctx& c, uint32_t feas) {
 // bytes) and the chosen one runs last.
 template <int RW>
 __device__ __forceinline__ void schedule_job(Ctx& c, uint64_t begin, uint32_t m, uint32_t bit, bool in_tmp,
-                                             uint64_t parent) {
+                                             uint64_t parent, JobRegs<RW>& jr, uint64_t nbegin, uint32_t nm,
+                                             bool ntmp) {
   const uint32_t KB = c.kf.kbits;
   const uint32_t feas = feasible_mask(c.p, m, bit, KB, true);
   uint32_t proc;
@@ -966,13 +1004,19 @@ __device__ __forceinline__ void schedule_job(Ctx& c, uint64_t begin, uint32_t m,
     for (uint32_t q = threadIdx.x; q < m; q += WG) store_rec<RW>(c.rec1, begin + q, load_rec<RW>(c.rec0, begin + q), false);
     src_tmp = true;
   }
+  // This job's records arrived in registers while the previous job ran:
+  // stage them (a sample re-reads its input for every run instead), then
+  // start loading the next job's records into the same registers.
+  const bool staged = !cf && m > 1;
+  if (staged) regs_stage<RW>(c, jr, m);
+  regs_load<RW>(c, jr, nbegin, nm, ntmp);
 #pragma unroll 1
   for (uint32_t k = cf ? 0u : 1u; k <= runs; k++) {
     const uint32_t q = cf ? (proc + k) % 3 : proc;
     if (!((feas >> q) & 1u) && cf) continue;
     __syncthreads();
     uint64_t t0 = now_ticks();
-    run_job<RW>(c, q, begin, m, src_tmp);
+    run_job<RW>(c, q, begin, m, src_tmp, staged);
     __syncthreads();
     if (k > 0) ticks[q] = (uint32_t)(now_ticks() - t0);
   }
@@ -1129,9 +1173,9 @@ __device__ __forceinline__ void finish_children(Ctx& c) {
 
 // A job of m <= C records by the chosen procedure.
 template <int RW>
-__device__ __forceinline__ void run_job(Ctx& c, uint32_t proc, uint64_t begin, uint32_t m, bool in_tmp) {
-  if (proc == P_RADIX) wg_radix_lds<RW>(c, begin, m, in_tmp);
-  else wg_finish<RW>(c, begin, m, in_tmp, proc == P_BITONIC ? P_BITONIC : P_LSD);
+__device__ __forceinline__ void run_job(Ctx& c, uint32_t proc, uint64_t begin, uint32_t m, bool in_tmp, bool staged) {
+  if (proc == P_RADIX) wg_radix_lds<RW>(c, begin, m, in_tmp, staged);
+  else wg_finish<RW>(c, begin, m, in_tmp, proc == P_BITONIC ? P_BITONIC : P_LSD, staged);
 }
 
 __device__ __forceinline__ void init_ctx(Ctx& c, const Plan& p, const Work& w, uint8_t* rec0, uint8_t* rec1,
@@ -1216,15 +1260,29 @@ __global__ __launch_bounds__(WG) void k_small_jobs(Plan p, Work w, uint8_t* rec0
   Ctx c;
   init_ctx(c, p, w, rec0, rec1, &S, dyn);
   const uint32_t nj = (uint32_t)min((uint64_t)w.ctl->nwg, p.cap_wg);
-  for (;;) {
+  // Each job is claimed one job ahead, and its records are loaded into
+  // registers while the workgroup sorts the job before it.
+  JobRegs<RW> jr;
+  if (threadIdx.x == 0) S.bcast = atomicAdd(&w.ctl->wg_head, 1u);
+  __syncthreads();
+  uint32_t idx = S.bcast;
+  __syncthreads();
+  if (idx < nj) {
+    const Bucket b = w.wgjobs[idx];
+    regs_load<RW>(c, jr, b.begin, (uint32_t)b.count, (b.flags & BF_TMP) != 0);
+  }
+  while (idx < nj) {
+    const Bucket b = w.wgjobs[idx];
     if (threadIdx.x == 0) S.bcast = atomicAdd(&w.ctl->wg_head, 1u);
     __syncthreads();
-    const uint32_t idx = S.bcast;
+    const uint32_t nidx = S.bcast;
     __syncthreads();
-    if (idx >= nj) break;
-    const Bucket b = w.wgjobs[idx];
+    Bucket nb{0, 0, 0, 0, 0};
+    if (nidx < nj) nb = w.wgjobs[nidx];
     if (threadIdx.x == 0) atomicAdd(&w.ctl->stage_records[2], (unsigned long long)b.count);
-    schedule_job<RW>(c, b.begin, (uint32_t)b.count, b.bit, (b.flags & BF_TMP) != 0, b.parent);
+    schedule_job<RW>(c, b.begin, (uint32_t)b.count, b.bit, (b.flags & BF_TMP) != 0, b.parent, jr, nb.begin,
+                     (uint32_t)nb.count, (nb.flags & BF_TMP) != 0);
+    idx = nidx;
   }
 }
 
