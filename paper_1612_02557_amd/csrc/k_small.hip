@@ -449,7 +449,8 @@ __device__ __forceinline__ Key stage_vary(Ctx& c, uint32_t m) {
   Key v{0, 0};
 #pragma unroll
   for (int q = 0; q < NWAVES; q++) { v.lo |= S.vary[2 * q]; v.hi |= S.vary[2 * q + 1]; }
-  __syncthreads();
+  // no barrier here: S.vary is written again only by the next job's stage,
+  // several barriers later
   return v;
 }
 
@@ -741,6 +742,9 @@ __device__ __forceinline__ void wg_finish(Ctx& c, uint64_t begin, uint32_t m, bo
 template <int RW>
 __device__ __forceinline__ void wg_radix_lds(Ctx& c, uint64_t begin, uint32_t m, bool in_tmp, bool staged) {
   SmallShared& S = *c.S;
+  uint32_t* cnt = S.wcnt;  // NWAVES * RB >= 1024 counters
+  // cleared before the stage's first barrier (the previous job ended with one)
+  for (uint32_t v = threadIdx.x; v < 1024; v += WG) cnt[v] = 0;
   Key vary;
   if (!wg_begin<RW>(c, begin, m, in_tmp, vary, staged)) return;
   const uint32_t lo = ctz128(vary);
@@ -758,31 +762,46 @@ __device__ __forceinline__ void wg_radix_lds(Ctx& c, uint64_t begin, uint32_t m,
   const uint32_t R = 1u << D;
   const uint32_t dsh = ib + W - D;
   const uint64_t wmask = W >= 64 ? ~0ull : ((1ull << W) - 1);
-  uint32_t* cnt = S.wcnt;  // NWAVES * RB >= 1024 counters
-  for (uint32_t v = threadIdx.x; v < R; v += WG) cnt[v] = 0;
-  __syncthreads();
   for (uint32_t q = threadIdx.x; q < m; q += WG) {
     uint64_t x = ((shr128(lds_key<RW>(stage, q, c.kf), lo).lo & wmask) << ib) | q;
     c0[q] = x;
     atomicAdd(&cnt[(uint32_t)(x >> dsh)], 1u);
   }
   __syncthreads();
-  block_excl_scan_lds(cnt, R, S.scan_tmp);
+  // counts -> sub-bucket starts (exclusive scan), and the largest count
+  {
+    const uint32_t t = threadIdx.x;
+    const uint32_t per = (R + WG - 1) / WG;
+    const uint32_t a = min(R, t * per), e = min(R, a + per);
+    uint32_t sum = 0, mx = 0;
+    for (uint32_t i = a; i < e; i++) { const uint32_t x = cnt[i]; sum += x; mx = max(mx, x); }
+    uint32_t wtot;
+    uint32_t ex = wave_excl_scan(sum, &wtot);
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, o));
+    if (lane_id() == 0) { S.scan_tmp[t / 64] = wtot; S.tcnt[t / 64] = mx; }
+    __syncthreads();
+    uint32_t base = 0, big = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < NWAVES; q++) {
+      if (q < t / 64) base += S.scan_tmp[q];
+      big = max(big, S.tcnt[q]);
+    }
+    uint32_t run = base + ex;
+    for (uint32_t i = a; i < e; i++) { const uint32_t x = cnt[i]; cnt[i] = run; run += x; }
+    S.bcast = big;  // the same value from every thread
+  }
+  __syncthreads();
+  if (S.bcast > INSERTION_MAX) {
+    wg_sort_staged<RW>(c, begin, m, m <= c.p.bitonic_max ? P_BITONIC : P_LSD, vary);
+    return;
+  }
   for (uint32_t q = threadIdx.x; q < m; q += WG) {
     uint64_t x = c0[q];
     c1[atomicAdd(&cnt[(uint32_t)(x >> dsh)], 1u)] = x;
   }
   __syncthreads();
   // cnt[v] is now the end of sub-bucket v
-  int big = 0;
-  for (uint32_t v = threadIdx.x; v < R; v += WG) {
-    const uint32_t s0 = v ? cnt[v - 1] : 0u;
-    if (cnt[v] - s0 > INSERTION_MAX) big = 1;
-  }
-  if (__syncthreads_or(big)) {
-    wg_sort_staged<RW>(c, begin, m, m <= c.p.bitonic_max ? P_BITONIC : P_LSD, vary);
-    return;
-  }
   for (uint32_t q = threadIdx.x; q < m; q += WG) {
     const uint64_t x = c1[q];
     const uint32_t v = (uint32_t)(x >> dsh);
@@ -1014,15 +1033,13 @@ __device__ __forceinline__ void schedule_job(Ctx& c, uint64_t begin, uint32_t m,
   for (uint32_t k = cf ? 0u : 1u; k <= runs; k++) {
     const uint32_t q = cf ? (proc + k) % 3 : proc;
     if (!((feas >> q) & 1u) && cf) continue;
-    __syncthreads();
+    if (cf) __syncthreads();
     uint64_t t0 = now_ticks();
-    run_job<RW>(c, q, begin, m, src_tmp, staged);
-    __syncthreads();
+    run_job<RW>(c, q, begin, m, src_tmp, staged);  // every procedure ends with a barrier
     if (k > 0) ticks[q] = (uint32_t)(now_ticks() - t0);
   }
   if (c.w.trace && __popc(feas) > 1 && threadIdx.x == 0)
     trace_row(c, m, parent, bit, proc, cf ? feas : (1u << proc), ticks, cf ? 1u : 0u);
-  __syncthreads();
 }
 
 // Group the children of the last radix pass into finishing jobs.  Children
