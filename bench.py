@@ -94,6 +94,107 @@ def cpu_baseline(pristine, key_bytes: int, sample_log2: int):
                       f"in {cores} threads, {dt:.2f} s wall"}
 
 
+def batched_check(rec, off, sizes, dists, spec, scratch, S):
+    """Exactness of a segmented sort with payload = global index, chunk by chunk
+    on the device: each output record equals the input record its payload
+    names, that record lies in the same segment, and (key, payload) strictly
+    increases inside each segment.  The input is regenerated into `scratch`."""
+    import numpy as np
+    import torch
+
+    from synth import device as sdev
+    s0 = 0
+    while s0 < S:
+        s1 = s0
+        while s1 < S and int(off[s1 + 1]) - int(off[s0]) <= (1 << 27):
+            s1 += 1
+        s1 = max(s1, s0 + 1)
+        a, b = int(off[s0]), int(off[s1])
+        if b > a:
+            sdev.generate_segments(spec, off, dists, out=scratch, segs=(s0, s1))
+            o = rec[a:b].view(torch.int64).view(b - a, -1)
+            key, idx = o[:, 0], o[:, 1]
+            seg = torch.repeat_interleave(torch.arange(s1 - s0, device="cuda"),
+                                          torch.from_numpy(sizes[s0:s1].astype(np.int64)).cuda())
+            lo = torch.from_numpy(off[s0:s1].astype(np.int64)).cuda()[seg]
+            hi = torch.from_numpy(off[s0 + 1:s1 + 1].astype(np.int64)).cuda()[seg]
+            if not bool(((idx >= lo) & (idx < hi)).all()):
+                return f"payload outside its segment in segments {s0}..{s1}"
+            if not torch.equal(scratch[idx], rec[a:b]):
+                return f"record differs from its input in segments {s0}..{s1}"
+            ks = key ^ torch.iinfo(torch.int64).min
+            same = seg[:-1] == seg[1:]
+            ok = (ks[:-1] < ks[1:]) | ((ks[:-1] == ks[1:]) & (idx[:-1] < idx[1:]))
+            if not bool((ok | ~same).all()):
+                return f"order broken in segments {s0}..{s1}"
+            del o, key, idx, seg, lo, hi, ks, same, ok
+        s0 = s1
+    return None
+
+
+def batched_main(args):
+    """Batched segmented sort (many independent arrays) in one call, against
+    one raduls_sort call per array, on the same device-resident input."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1612_02557_amd import raduls
+    from synth import device as sdev
+    raduls.lib()
+    S = args.segs
+    sizes = synth.segment_sizes(S, args.seed, args.seg_lo, args.seg_hi)
+    off = synth.segment_offsets(sizes)
+    dists = synth.segment_dists(S, args.seed)
+    n = int(off[-1])
+    spec = synth.Spec(n=n, rec_bytes=16, key_bytes=8, payload="index", seed=args.seed)
+    log(f"{S} segments, sizes log-uniform in [{args.seg_lo}, {args.seg_hi}], {n} records in all")
+    rec = sdev.generate_segments(spec, off, dists)
+    tmp = torch.empty_like(rec)
+    doff = torch.from_numpy(off.astype(np.int64)).cuda()
+    raduls.set_scheduler(raduls.SCHED_HEURISTIC)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        sdev.generate_segments(spec, off, dists, out=rec)
+        torch.cuda.synchronize()
+        ev0.record()
+        fn()
+        ev1.record()
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1)
+
+    def batched():
+        raduls.sort_segmented(rec, doff, 8, tmp)
+
+    def per_array():
+        for s in range(S):
+            a, b = int(off[s]), int(off[s + 1])
+            if b - a > 1:
+                raduls.sort(rec[a:b], 8, tmp[a:b])
+
+    for _ in range(args.warmup):
+        timed(batched)
+    tb = [timed(batched) for _ in range(args.steps)]
+    raduls.sync_check()
+    err = batched_check(rec, off, sizes, dists, spec, tmp, S)
+    if err:
+        log(f"VERIFICATION FAILED: {err}")
+    timed(per_array)
+    tp = [timed(per_array) for _ in range(max(1, args.steps // 2))]
+    mb, mp = statistics.median(tb), statistics.median(tp)
+    out = {"metric": "batched segmented sort, records/s (one call vs one call per array)",
+           "value": n / (mb / 1e3), "unit": "records/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": mb, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+           "data": "synthetic",
+           "config": {"workload": f"{S} independent arrays of 16-byte records, sizes log-uniform in "
+                                  f"[{args.seg_lo}, {args.seg_hi}], uniform or Zipf keys per array (seed {args.seed})",
+                      "segments": S, "records": n},
+           "per_array_ms": mp, "per_array_value": n / (mp / 1e3), "batched_over_per_array": mp / mb,
+           "verified": err is None, "step_ms": tb, "per_array_step_ms": tp}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -108,12 +209,19 @@ def main():
     ap.add_argument("--cpu-sample-log2", type=int, default=26)
     ap.add_argument("--phases", type=int, default=1, help="1: per-phase events during the timed steps")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-scheduler leg")
+    ap.add_argument("--batched", action="store_true", help="batched segmented sort vs one call per array")
+    ap.add_argument("--segs", type=int, default=10000)
+    ap.add_argument("--seg-lo", type=int, default=1 << 10)
+    ap.add_argument("--seg-hi", type=int, default=1 << 22)
     args = ap.parse_args()
 
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               f"(the batched and single-array paths are single-GPU; see DESIGN.md for sharding)", file=sys.stderr)
         sys.exit(2)
+
+    if args.batched:
+        return batched_main(args)
 
     import torch
 

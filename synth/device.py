@@ -82,14 +82,18 @@ def generate(spec: gen.Spec, device="cuda"):
     return fill(out, spec)
 
 
-def generate_segments(spec: gen.Spec, off: np.ndarray, dists: np.ndarray, device="cuda"):
-    """All records of a batch (segment s with key distribution dists[s]); global index payload."""
+def generate_segments(spec: gen.Spec, off: np.ndarray, dists: np.ndarray, device="cuda", out=None, segs=None):
+    """All records of a batch (segment s with key distribution dists[s]); global index payload.
+
+    With ``out`` the records are written there; with ``segs = (s0, s1)`` only
+    segments s0 .. s1-1 are written (at their global positions in ``out``).
+    """
     import torch
     n = int(off[-1])
-    out = torch.empty((n, spec.rec_bytes), dtype=torch.uint8, device=device)
+    if out is None:
+        out = torch.empty((n, spec.rec_bytes), dtype=torch.uint8, device=device)
     # consecutive segments of one distribution are filled by one launch
-    s = 0
-    S = len(dists)
+    s, S = (0, len(dists)) if segs is None else segs
     while s < S:
         e = s
         while e + 1 < S and dists[e + 1] == dists[s]:
