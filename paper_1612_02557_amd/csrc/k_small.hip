@@ -846,8 +846,9 @@ __device__ __forceinline__ bool block_pass(Ctx& c, const Bucket& b) {
     d = min(c.p.d_block, KB - bit);
     R = 1u << d;
     shift = KB - bit - d;
-    for (uint32_t v = threadIdx.x; v < R; v += WG) S.hist[v] = 0;
+    for (uint32_t v = threadIdx.x; v < NWAVES * RB; v += WG) S.wcnt[v] = 0;
     __syncthreads();
+    uint32_t* wh = &S.wcnt[wave * RB];  // this wave's counters
     uint64_t vlo = 0, vhi = 0;
     for (uint32_t q0 = 0; q0 < m; q0 += WG * 16) {
       Key kk[16];
@@ -863,15 +864,26 @@ __device__ __forceinline__ bool block_pass(Ctx& c, const Bucket& b) {
         vlo |= kk[u].lo ^ ref.lo;
         vhi |= kk[u].hi ^ ref.hi;
         uint32_t v = key_digit(kk[u], shift, R - 1, c.kf);
-        uint64_t active = __ballot(valid);
-        uint64_t peers = match_digit(v, d, active);
-        if (valid && (uint32_t)(__ffsll((long long)peers) - 1) == lane) atomicAdd(&S.hist[v], (uint32_t)__popcll(peers));
+        // one LDS add per key, or one per wave when all 64 keys share the digit
+        const uint64_t active = __ballot(valid);
+        const uint32_t v0 = __shfl(v, 0);
+        if (active == ~0ull && __ballot(v == v0) == ~0ull) {
+          if (lane == 0) atomicAdd(&wh[v0], 64u);
+        } else if (valid) {
+          atomicAdd(&wh[v], 1u);
+        }
       }
     }
     vlo = wave_or64(vlo);
     vhi = wave_or64(vhi);
     if (lane == 0) { S.vary[2 * wave] = vlo; S.vary[2 * wave + 1] = vhi; }
     __syncthreads();
+    for (uint32_t v = threadIdx.x; v < R; v += WG) {
+      uint32_t h = 0;
+#pragma unroll
+      for (int q = 0; q < NWAVES; q++) h += S.wcnt[q * RB + v];
+      S.hist[v] = h;
+    }
     Key vary{0, 0};
 #pragma unroll
     for (int q = 0; q < NWAVES; q++) { vary.lo |= S.vary[2 * q]; vary.hi |= S.vary[2 * q + 1]; }
@@ -905,18 +917,22 @@ __device__ __forceinline__ bool block_pass(Ctx& c, const Bucket& b) {
   const uint32_t per_wave = BT / NWAVES;
   const uint32_t IPT = BT / WG;
   constexpr uint32_t IPT_MAX = (RW >= 2 ? 64 / RW : 32) < IPT_BLOCK ? (RW >= 2 ? 64 / RW : 32) : IPT_BLOCK;
-  for (uint32_t t0 = 0; t0 < m; t0 += BT) {
-    const uint32_t cnt = min(BT, m - t0);
-    for (uint32_t i = threadIdx.x; i < NWAVES * RB; i += WG) S.wcnt[i] = 0;
-    __syncthreads();
-    Rec<RW> rec[IPT_MAX];
-    uint32_t dg[IPT_MAX], rk[IPT_MAX];
-    const uint32_t wb = t0 + wave * per_wave;
+  // each tile's records are loaded while the tile before it is written out
+  Rec<RW> rec[IPT_MAX];
+  auto load_tile = [&](uint32_t t) {
 #pragma unroll
     for (uint32_t j = 0; j < IPT_MAX; j++) {
-      uint32_t q = wb + j * 64 + lane;
+      uint32_t q = t + wave * per_wave + j * 64 + lane;
       if (j < IPT && q < m) rec[j] = load_rec<RW>(src, b.begin + q);
     }
+  };
+  for (uint32_t i = threadIdx.x; i < NWAVES * RB; i += WG) S.wcnt[i] = 0;
+  load_tile(0);
+  __syncthreads();
+  for (uint32_t t0 = 0; t0 < m; t0 += BT) {
+    const uint32_t cnt = min(BT, m - t0);
+    uint32_t dg[IPT_MAX], rk[IPT_MAX];
+    const uint32_t wb = t0 + wave * per_wave;
     RankPart rp[IPT_MAX];
 #pragma unroll
     for (uint32_t j = 0; j < IPT_MAX; j++) {
@@ -937,6 +953,7 @@ __device__ __forceinline__ bool block_pass(Ctx& c, const Bucket& b) {
       uint32_t q = wb + j * 64 + lane;
       if (j < IPT && q < m) lds_put<RW>(c.dyn, S.toff[dg[j]] + S.wcnt[wave * RB + dg[j]] + rk[j], rec[j]);
     }
+    if (t0 + BT < m) load_tile(t0 + BT);
     __syncthreads();
     for (uint32_t q = threadIdx.x; q < cnt; q += WG) {
       Rec<RW> r = lds_get<RW>(c.dyn, q);
@@ -945,6 +962,7 @@ __device__ __forceinline__ bool block_pass(Ctx& c, const Bucket& b) {
     }
     __syncthreads();
     for (uint32_t v = threadIdx.x; v < R; v += WG) S.run[v] += S.tcnt[v];
+    for (uint32_t i = threadIdx.x; i < NWAVES * RB; i += WG) S.wcnt[i] = 0;
     __syncthreads();
   }
   return true;
