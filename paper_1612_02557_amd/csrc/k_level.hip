@@ -360,19 +360,27 @@ __global__ __launch_bounds__(WG) void k_scatter(Plan p, Work w, uint32_t level, 
   const uint64_t epoch = (uint64_t)((w.ctl->epoch + level) & 0x3FFFFFu) << LB_EPOCH_SHIFT;
   const bool nt = p.nontemporal != 0;
 
+  // The next tile is claimed, and the per-wave counters cleared, just before
+  // a tile's last barrier.
+  auto claim = [&]() {
+    uint64_t tk = atomicAdd(&w.ctl->ticket[level], 1u);
+    sticket = tk;
+    sb = tk < T ? find_entry(start, nb, tk) : 0;
+  };
+  for (uint32_t i = threadIdx.x; i < NWAVES * RMAX; i += WG) wcnt[i] = 0;
+  if (threadIdx.x == 0) claim();
+  __syncthreads();
   for (;;) {
-    if (threadIdx.x == 0) {
-      uint64_t tk = atomicAdd(&w.ctl->ticket[level], 1u);
-      sticket = tk;
-      sb = tk < T ? find_entry(start, nb, tk) : 0;
-    }
-    __syncthreads();
-    uint64_t ticket = sticket;
-    uint32_t b = sb;
-    __syncthreads();
+    const uint64_t ticket = sticket;
+    const uint32_t b = sb;
     if (ticket >= T) break;
     Bucket B = list[b];
-    if (B.flags & BF_SKIP) continue;
+    if (B.flags & BF_SKIP) {
+      __syncthreads();  // everyone has read the ticket
+      if (threadIdx.x == 0) claim();
+      __syncthreads();
+      continue;
+    }
     uint64_t ti = ticket - start[b];
     uint64_t r0 = B.begin + ti * p.tile;
     uint64_t bend = B.begin + B.count;
@@ -383,9 +391,6 @@ __global__ __launch_bounds__(WG) void k_scatter(Plan p, Work w, uint32_t level, 
     uint32_t mask = R - 1u;
     const uint8_t* src = (B.flags & BF_TMP) ? rec1 : rec0;
     uint8_t* dst = (B.flags & BF_TMP) ? rec0w : rec1w;
-
-    for (uint32_t i = threadIdx.x; i < NWAVES * R; i += WG) wcnt[(i / R) * RMAX + (i % R)] = 0;
-    __syncthreads();
 
     Rec<RW> rec[IPT_MAX];
     uint32_t dg[IPT_MAX];
@@ -467,6 +472,8 @@ __global__ __launch_bounds__(WG) void k_scatter(Plan p, Work w, uint32_t level, 
       uint32_t v = key_digit(rec_key<RW>(r, kf), shift, mask, kf);
       store_rec<RW>(dst, gbase[v] + q, r, nt);
     }
+    for (uint32_t i = threadIdx.x; i < NWAVES * RMAX; i += WG) wcnt[i] = 0;
+    if (threadIdx.x == 0) claim();
     __syncthreads();
   }
 }

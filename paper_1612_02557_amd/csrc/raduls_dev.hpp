@@ -287,26 +287,27 @@ __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t x, uint32_t* total) 
 }
 
 // Block-wide exclusive scan of `count` uint32 values in LDS (in place),
-// count <= 16 * WG.  Uses `tmp` (NWAVES + 1 words of LDS).  Returns the total.
+// count <= 16 * WG.  Uses `tmp` (NWAVES words of LDS).  Returns the total.
+// Two barriers: every thread adds up the wave totals before its own.
 __device__ __forceinline__ uint32_t block_excl_scan_lds(uint32_t* a, uint32_t count, uint32_t* tmp) {
   const uint32_t t = threadIdx.x;
   const uint32_t per = (count + WG - 1) / WG;  // contiguous run per thread
-  uint32_t lo = t * per, hi = min(lo + per, count);
+  uint32_t lo = min(count, t * per), hi = min(lo + per, count);
   uint32_t s = 0;
   for (uint32_t i = lo; i < hi; i++) s += a[i];
   uint32_t wtot;
   uint32_t ex = wave_excl_scan(s, &wtot);
   if (lane_id() == 0) tmp[t / 64] = wtot;
   __syncthreads();
-  if (t == 0) {
-    uint32_t run = 0;
-    for (int w = 0; w < NWAVES; w++) { uint32_t c = tmp[w]; tmp[w] = run; run += c; }
-    tmp[NWAVES] = run;
+  uint32_t base = 0, total = 0;
+#pragma unroll
+  for (uint32_t w = 0; w < NWAVES; w++) {
+    const uint32_t x = tmp[w];
+    base += w < t / 64 ? x : 0u;
+    total += x;
   }
-  __syncthreads();
-  uint32_t run = tmp[t / 64] + ex;
+  uint32_t run = base + ex;
   for (uint32_t i = lo; i < hi; i++) { uint32_t c = a[i]; a[i] = run; run += c; }
-  uint32_t total = tmp[NWAVES];
   __syncthreads();
   return total;
 }
