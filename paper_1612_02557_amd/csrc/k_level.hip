@@ -418,12 +418,17 @@ __global__ __launch_bounds__(WG) void k_scatter(Plan p, Work w, uint32_t level, 
     for (uint32_t j = 0; j < IPT_MAX; j++)
       if (j < IPT) rk[j] = rank_finish(rp[j]);
     __syncthreads();
+    // the tile's digit counts are known: publish them for the tiles after
+    // it as early as possible (the first tile of a bucket publishes an
+    // inclusive word at once)
+    uint64_t* st = w.status + ticket * RS;
     for (uint32_t v = threadIdx.x; v < R; v += WG) {
       uint32_t s = 0;
 #pragma unroll
       for (int q = 0; q < NWAVES; q++) { uint32_t c = wcnt[q * RMAX + v]; wcnt[q * RMAX + v] = s; s += c; }
       tcnt[v] = s;
       toff[v] = s;
+      atomic_store_agent(&st[v], epoch | (ti == 0 ? LB_INC : LB_AGG) | (uint64_t)s);
     }
     __syncthreads();
     block_excl_scan_lds(toff, R, sscan);
@@ -439,15 +444,11 @@ __global__ __launch_bounds__(WG) void k_scatter(Plan p, Work w, uint32_t level, 
       }
     }
     // decoupled look-back, one digit per thread
-    uint64_t* st = w.status + ticket * RS;
     const uint64_t* dbase = w.hist + (uint64_t)b * RS;
     for (uint32_t v = threadIdx.x; v < R; v += WG) {
       uint64_t c = tcnt[v];
       uint64_t excl = 0;
-      if (ti == 0) {
-        atomic_store_agent(&st[v], epoch | LB_INC | c);
-      } else {
-        atomic_store_agent(&st[v], epoch | LB_AGG | c);
+      if (ti != 0) {
         uint64_t j = ticket - 1;
         uint32_t spins = 0;
         for (;;) {
