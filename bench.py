@@ -266,12 +266,10 @@ def main():
     ms_per_step = statistics.mean(times)
     value = n / (ms_per_step / 1e3)
 
-    verified = None
-    if r == 16 and k == 8:
-        err = exact_index_check(rec, pristine)
-        verified = err is None
-        if err:
-            log(f"VERIFICATION FAILED: {err}")
+    err = exact_index_check(rec, pristine, r, k)
+    verified = None if err == "unchecked" else err is None
+    if err and err != "unchecked":
+        log(f"VERIFICATION FAILED: {err}")
     try:
         raduls.sync_check()
     except raduls.RadulsError as e:
@@ -353,9 +351,8 @@ def main():
         raduls.set_timing(1)
         step()
         lt = [step() for _ in range(args.steps)]
-        lok = None
-        if r == 16 and k == 8:
-            lok = exact_index_check(rec, pristine) is None
+        lerr = exact_index_check(rec, pristine, r, k)
+        lok = None if lerr == "unchecked" else lerr is None
         raduls.set_scheduler(raduls.SCHED_HEURISTIC)
         raduls.unload_model()
         lms = statistics.mean(lt)

@@ -568,7 +568,7 @@ __device__ __forceinline__ void lds_pass64(SmallShared& S, const uint64_t* src, 
 //   BITONIC a bitonic network on the (unique) composites
 // When the varying bits and the index do not fit in 64 bits, LSD refines a
 // permutation reading the keys from the stage, and BITONIC sorts 128-bit
-// composites.
+// composites (or, above 128 bits, takes the LSD refinement too).
 template <int RW>
 __device__ __forceinline__ void wg_sort_staged(Ctx& c, uint64_t begin, uint32_t m, uint32_t proc, Key vary) {
   SmallShared& S = *c.S;
@@ -622,7 +622,7 @@ __device__ __forceinline__ void wg_sort_staged(Ctx& c, uint64_t begin, uint32_t 
     __syncthreads();
     return;
   }
-  if (proc == P_BITONIC && P <= C) {
+  if (proc == P_BITONIC && P <= C && W + ib <= 128) {
     uint64_t* cl = c0;
     uint64_t* ch = c0 + P;
     for (uint32_t q = threadIdx.x; q < P; q += WG) {
@@ -738,7 +738,10 @@ __device__ __forceinline__ void wg_finish(Ctx& c, uint64_t begin, uint32_t m, bo
 // above 32 composites (a skewed job: runs of equal keys) makes the workgroup
 // finish the job from the same stage by the bitonic network instead (by LSD
 // if the job exceeds the bitonic capacity), which costs the same whatever
-// the duplicates.
+// the duplicates.  With wide keys (varying bits plus index
+// bits above 64) the composite keeps only the top varying bits, and
+// composites that tie there are ordered by the staged full keys, then by
+// index, so the slots stay exact.
 template <int RW>
 __device__ __forceinline__ void wg_radix_lds(Ctx& c, uint64_t begin, uint32_t m, bool in_tmp, bool staged) {
   SmallShared& S = *c.S;
@@ -750,20 +753,23 @@ __device__ __forceinline__ void wg_radix_lds(Ctx& c, uint64_t begin, uint32_t m,
   const uint32_t lo = ctz128(vary);
   const uint32_t W = bitlen128(vary) - lo;
   const uint32_t ib = 32 - __clz(m - 1);
-  if (W + ib > 64) {
-    wg_sort_staged<RW>(c, begin, m, P_LSD, vary);
-    return;
-  }
+  // the composite holds the top Wt varying bits; when that drops some
+  // (wide keys), equal composite keys are ordered by the full key from the
+  // stage, then by index
+  const uint32_t Wt = min(W, 64 - ib);
+  const bool trunc = Wt < W;
   const uint32_t C = c.p.c_fin;
   const uint32_t* stage = c.dyn;
   uint64_t* c0 = reinterpret_cast<uint64_t*>(c.dyn + C * RW);
   uint64_t* c1 = c0 + C;
-  const uint32_t D = min(10u, W);
+  const uint32_t D = min(10u, Wt);
   const uint32_t R = 1u << D;
-  const uint32_t dsh = ib + W - D;
-  const uint64_t wmask = W >= 64 ? ~0ull : ((1ull << W) - 1);
+  const uint32_t dsh = ib + Wt - D;
+  const uint32_t ksh = lo + W - Wt;
+  const uint64_t wmask = Wt >= 64 ? ~0ull : ((1ull << Wt) - 1);
+  const uint64_t imask = (1ull << ib) - 1;
   for (uint32_t q = threadIdx.x; q < m; q += WG) {
-    uint64_t x = ((shr128(lds_key<RW>(stage, q, c.kf), lo).lo & wmask) << ib) | q;
+    uint64_t x = ((shr128(lds_key<RW>(stage, q, c.kf), ksh).lo & wmask) << ib) | q;
     c0[q] = x;
     atomicAdd(&cnt[(uint32_t)(x >> dsh)], 1u);
   }
@@ -807,11 +813,26 @@ __device__ __forceinline__ void wg_radix_lds(Ctx& c, uint64_t begin, uint32_t m,
     const uint32_t v = (uint32_t)(x >> dsh);
     const uint32_t s0 = v ? cnt[v - 1] : 0u, e = cnt[v];
     uint32_t below = 0;
-    for (uint32_t i = s0; i < e; i++) below += c1[i] < x ? 1u : 0u;
+    if (!trunc) {
+      for (uint32_t i = s0; i < e; i++) below += c1[i] < x ? 1u : 0u;
+    } else {
+      const uint64_t xk = x >> ib;
+      const uint32_t xi = (uint32_t)(x & imask);
+      for (uint32_t i = s0; i < e; i++) {
+        const uint64_t y = c1[i];
+        const uint64_t yk = y >> ib;
+        bool lt = yk < xk;
+        if (yk == xk && y != x) {
+          const Key ky = lds_key<RW>(stage, (uint32_t)(y & imask), c.kf);
+          const Key kx = lds_key<RW>(stage, xi, c.kf);
+          lt = key_less(ky, kx) || (!key_less(kx, ky) && (uint32_t)(y & imask) < xi);
+        }
+        below += lt ? 1u : 0u;
+      }
+    }
     c0[s0 + below] = x;
   }
   __syncthreads();
-  const uint64_t imask = (1ull << ib) - 1;
   for (uint32_t q = threadIdx.x; q < m; q += WG)
     store_rec<RW>(c.rec0, begin + q, lds_get<RW>(stage, (uint32_t)(c0[q] & imask)), false);
   __syncthreads();

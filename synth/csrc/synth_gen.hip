@@ -78,15 +78,20 @@ extern "C" int synth_fill(void* out, uint64_t i0, uint64_t count, uint32_t rec_b
   B.salt_lo = bases[4]; B.salt_hi = bases[5];
   for (int w = 0; w < 16; w++) B.payload[w] = bases[6 + w];
   B.p24 = bases[22];
-  uint64_t blocks = (count + 255) / 256;
-  if (blocks > 0x7FFFFFFFull) return -2;
-  (void)hipGetLastError();  // report this launch's status only
-  hipLaunchKernelGGL(k_fill, dim3((uint32_t)blocks), dim3(256), 0, (hipStream_t)stream, (uint32_t*)out, i0, count,
-                     rec_bytes, key_bytes, dist, payload_index, B, cdf, m);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) {
-    fprintf(stderr, "synth_fill: %s\n", hipGetErrorString(e));
-    return -3;
+  (void)hipGetLastError();  // report this call's launches only
+  // a launch covers fewer than 2^32 work-items: fill 2^30 records per launch
+  const uint64_t step = 1ull << 30;
+  for (uint64_t a = 0; a < count; a += step) {
+    const uint64_t c = count - a < step ? count - a : step;
+    const uint64_t blocks = (c + 255) / 256;
+    hipLaunchKernelGGL(k_fill, dim3((uint32_t)blocks), dim3(256), 0, (hipStream_t)stream,
+                       (uint32_t*)out + a * (rec_bytes / 4), i0 + a, c, rec_bytes, key_bytes, dist, payload_index, B,
+                       cdf, m);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+      fprintf(stderr, "synth_fill: %s\n", hipGetErrorString(e));
+      return -3;
+    }
   }
   return 0;
 }

@@ -22,30 +22,72 @@ def first_diff(got: np.ndarray, want: np.ndarray) -> str:
     return f"{len(bad)} records differ, first at {i}: got {got[i].tolist()} want {want[i].tolist()}"
 
 
-def exact_index_check(out_dev, inp_dev, key_bytes: int = 8):
-    """Exactness test for 16-byte records with an 8-byte key and payload = index.
+def _ukey(w):
+    """Unsigned 64-bit order as signed order."""
+    import torch
+    return w ^ torch.iinfo(torch.int64).min
 
-    The output equals the stable sort of the input iff (i) every output record
-    equals the input record its payload names and (ii) (key, payload) strictly
-    increases along the output (then the payloads are distinct, the output is
-    a permutation of the input, and the order is the unique stable order).
-    Runs on the device with torch ops; returns None or a message.
+
+def _lex_less(a, b):
+    """Elementwise a < b for lists of equal-length int64 columns, most significant first."""
+    lt = a[-1] < b[-1]
+    for x, y in zip(reversed(a[:-1]), reversed(b[:-1])):
+        lt = (x < y) | ((x == y) & lt)
+    return lt
+
+
+def exact_index_check(out_dev, inp_dev, rec_bytes: int = 16, key_bytes: int = 8, chunk: int = 1 << 27):
+    """Exactness test of a device sort, run on the device with torch ops.
+
+    Records whose key is 8 or 16 bytes and whose next 8 bytes hold the input
+    index (the generator's ``index`` payload): the output equals the stable
+    sort of the input iff (i) every output record equals the input record its
+    payload names and (ii) (key, payload) strictly increases along the output
+    (then the payloads are distinct, the output is a permutation of the input,
+    and the order is the unique stable order).  Checked ``chunk`` records at a
+    time, so that the check of a 2^32-record sort fits next to its buffers.
+    Key-only records (rec_bytes == key_bytes in {8, 16}): the output equals
+    the input keys sorted by torch (two stable passes for 16-byte keys).
+    Returns None (exact), a message, or "unchecked" for other formats.
     """
     import torch
     n = out_dev.shape[0]
     if n == 0:
         return None
+    if key_bytes not in (8, 16) or rec_bytes % 8:
+        return "unchecked"
+    kw = key_bytes // 8
+    if rec_bytes == key_bytes:
+        o = out_dev.view(torch.int64).view(n, kw)
+        i = inp_dev.view(torch.int64).view(n, kw)
+        perm = torch.sort(_ukey(i[:, 0]), stable=True).indices
+        if kw == 2:
+            hi = _ukey(i[:, 1])[perm]
+            perm = perm[torch.sort(hi, stable=True).indices]
+            del hi
+        for a in range(0, n, chunk):
+            b = min(n, a + chunk)
+            if not torch.equal(i[perm[a:b]], o[a:b]):
+                return f"output in [{a}, {b}) is not the sorted input"
+        return None
+    if rec_bytes < key_bytes + 8:
+        return "unchecked"
     o = out_dev.view(torch.int64).view(n, -1)
-    key = o[:, 0]
-    idx = o[:, 1]
-    if int(idx.min()) < 0 or int(idx.max()) >= n:
-        return "payload out of range"
-    if not torch.equal(inp_dev[idx], out_dev):
-        return "an output record differs from the input record its payload names"
-    ks = key ^ torch.iinfo(torch.int64).min  # unsigned order as signed order
-    a, b = ks[:-1], ks[1:]
-    ok = (a < b) | ((a == b) & (idx[:-1] < idx[1:]))
-    if not bool(ok.all()):
-        j = int(torch.nonzero(~ok)[0])
-        return f"order broken at {j}"
+    prev = None
+    for a in range(0, n, chunk):
+        b = min(n, a + chunk)
+        idx = o[a:b, kw]
+        if int(idx.min()) < 0 or int(idx.max()) >= n:
+            return "payload out of range"
+        if not torch.equal(inp_dev[idx], out_dev[a:b]):
+            return f"an output record in [{a}, {b}) differs from the input record its payload names"
+        cols = [_ukey(o[a:b, w]) for w in reversed(range(kw))] + [idx]   # most significant first
+        if prev is not None:
+            cols = [torch.cat([p, c]) for p, c in zip(prev, cols)]
+        ok = _lex_less([c[:-1] for c in cols], [c[1:] for c in cols])
+        if not bool(ok.all()):
+            j = int(torch.nonzero(~ok)[0]) + a - (1 if prev is not None else 0)
+            return f"order broken at {j}"
+        prev = [c[-1:].clone() for c in cols]
+        del cols, ok
     return None

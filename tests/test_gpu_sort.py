@@ -93,6 +93,37 @@ def test_adversarial(R, n, rng):
         check(R, _records_with_keys(keys), 8, f"adversarial {name} n={n}")
 
 
+def _wide_records(hi, lo, r=32):
+    n = len(hi)
+    rec = np.zeros((n, r), dtype=np.uint8)
+    rec[:, :8] = np.asarray(lo, dtype="<u8").view(np.uint8).reshape(n, 8)
+    rec[:, 8:16] = np.asarray(hi, dtype="<u8").view(np.uint8).reshape(n, 8)
+    rec[:, 16:24] = np.arange(n, dtype="<u8").view(np.uint8).reshape(n, 8)
+    return rec
+
+
+@pytest.mark.parametrize("sched", ["heuristic", "RADIX"])
+@pytest.mark.parametrize("n", [5000, 300_000])
+def test_wide_keys_split_varying_bits(R, n, sched, rng):
+    """16-byte keys whose varying bits sit at both ends of the key: the
+    in-LDS radix composite keeps only the top varying bits, so keys that tie
+    there and differ in the low bits (and exact duplicates) test the full-key
+    tie rule."""
+    const_hi, const_lo = np.uint64(0x0123456789ABCDEF), np.uint64(0xFEDCBA9876543210)
+    cases = {}
+    for top, low in ((4, 3), (6, 6), (10, 8), (16, 1)):
+        hi = (rng.integers(0, 1 << top, n, dtype=np.uint64) << np.uint64(64 - top)) | (const_hi >> np.uint64(top))
+        lo = ((const_lo >> np.uint64(low)) << np.uint64(low)) | rng.integers(0, 1 << low, n, dtype=np.uint64)
+        cases[f"top{top}_low{low}"] = (hi, lo)
+    if sched == "RADIX":
+        R.set_scheduler(R.SCHED_FORCED, R.PROC_RADIX)
+    try:
+        for name, (hi, lo) in cases.items():
+            check(R, _wide_records(hi, lo), 16, f"wide split {name} n={n} {sched}")
+    finally:
+        R.set_scheduler(R.SCHED_HEURISTIC)
+
+
 def test_empty_and_single(R):
     import torch
     for n in (0, 1):
