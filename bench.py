@@ -209,6 +209,7 @@ def main():
     ap.add_argument("--cpu-sample-log2", type=int, default=26)
     ap.add_argument("--phases", type=int, default=1, help="1: per-phase events during the timed steps")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-scheduler leg")
+    ap.add_argument("--tuning", default="", help="tuning overrides, e.g. big_min=8192,workgroups_per_cu=3")
     ap.add_argument("--batched", action="store_true", help="batched segmented sort vs one call per array")
     ap.add_argument("--segs", type=int, default=10000)
     ap.add_argument("--seg-lo", type=int, default=1 << 10)
@@ -241,6 +242,16 @@ def main():
     torch.cuda.synchronize()
     raduls.set_scheduler(raduls.SCHED_HEURISTIC)
     raduls.set_timing(2 if args.phases else 1)
+    tuning = None
+    if args.tuning:
+        t = raduls.default_tuning(r, k, n)
+        for kv in args.tuning.split(","):
+            key, val = kv.split("=")
+            if not hasattr(t, key):
+                raise SystemExit(f"unknown tuning field {key}")
+            setattr(t, key, int(val))
+        raduls.set_tuning(t)
+        tuning = t.as_dict()
 
     def step():
         rec.copy_(pristine)
@@ -331,7 +342,7 @@ def main():
         "config": {"workload": f"sort 2^{args.log2n} records of {r} bytes, {args.dist} {k}-byte keys, "
                                f"payload = original index (seed {args.seed})",
                    "n": n, "rec_bytes": r, "key_bytes": k, "dist": args.dist, "seed": args.seed,
-                   "scheduler": "heuristic"},
+                   "scheduler": "heuristic", **({"tuning": tuning} if tuning else {})},
         "roofline": roof,
         "e2e": {"model_bytes_per_record": bpr, "t_roof_ms": t_roof_ms, "frac": t_roof_ms / ms_per_step,
                 "model_GBps": bpr * n / (ms_per_step / 1e3) / 1e9},

@@ -44,6 +44,10 @@ struct SmallShared {
   uint64_t cbegin, cparent;
   uint32_t sp;
   uint32_t bcast;
+  // the scheduler network, copied from global memory when it is in use,
+  // with the layer-2 matrix transposed (lane j then reads its column of a
+  // row of the matrix without bank conflicts)
+  float model[MLP_MODEL_FLOATS];
   uint32_t decisions;
   Bucket item;
 };
@@ -56,6 +60,7 @@ struct Ctx {
   KeyFmt kf;
   SmallShared* S;
   uint32_t* dyn;     // dynamic LDS
+  const float* model;  // the network in LDS, or null
   Bucket* stack;
 };
 
@@ -1036,18 +1041,12 @@ __device__ __forceinline__ void schedule_job(Ctx& c, uint64_t begin, uint32_t m,
   const uint32_t KB = c.kf.kbits;
   const uint32_t feas = feasible_mask(c.p, m, bit, KB, true);
   uint32_t proc;
-  if (c.p.sched_mode == RADULS_SCHED_LEARNED && c.w.model && __popc(feas) > 1) {
-    // the network is evaluated by one wavefront and its choice shared
-    SmallShared& S = *c.S;
-    if (threadIdx.x < 64) {
-      const uint32_t pr = choose_proc_wave(c.p, c.w.model, m, parent, bit, KB, feas);
-      if (threadIdx.x == 0) S.bcast = pr;
-    }
-    __syncthreads();
-    proc = S.bcast;
-    __syncthreads();
+  if (c.p.sched_mode == RADULS_SCHED_LEARNED && c.model && __popc(feas) > 1) {
+    // every wavefront evaluates the network on the same inputs by the same
+    // instructions, so all reach the same choice without a barrier
+    proc = choose_proc_wave<true>(c.p, c.model, m, parent, bit, KB, feas);
   } else {
-    proc = choose_proc(c.p, c.w.model, m, parent, bit, KB, feas);
+    proc = choose_proc<true>(c.p, c.model, m, parent, bit, KB, feas);
   }
   const bool cf = sample_job(c, feas);
   const uint32_t runs = cf ? 3u : 1u;
@@ -1145,7 +1144,7 @@ __device__ __forceinline__ void build_jobs(Ctx& c) {
     }
     if (m <= TINY_MAX || (m <= WSC && (KB - bit) + ib <= 128)) {
       uint32_t feas = m > TINY_MAX ? feasible_mask(c.p, m, bit, KB, false) : 0u;
-      uint32_t proc = __popc(feas) > 1 ? choose_proc(c.p, c.w.model, m, parent, bit, KB, feas)
+      uint32_t proc = __popc(feas) > 1 ? choose_proc<true>(c.p, c.model, m, parent, bit, KB, feas)
                                        : (feas ? (uint32_t)(__ffs(feas) - 1) : P_LSD);
       uint32_t sampled = 0;
       if (c.w.trace && c.p.sample_period && __popc(feas) > 1) {
@@ -1244,6 +1243,16 @@ __device__ __forceinline__ void init_ctx(Ctx& c, const Plan& p, const Work& w, u
   c.S = S;
   c.dyn = dyn;
   c.stack = w.stacks + (uint64_t)blockIdx.x * p.stack_cap;
+  c.model = nullptr;
+  if (p.sched_mode == RADULS_SCHED_LEARNED && w.model) {
+    constexpr uint32_t W2 = MLP_H * MLP_F + MLP_H, W2E = W2 + MLP_H * MLP_H;
+    for (uint32_t i = threadIdx.x; i < MLP_MODEL_FLOATS; i += WG) {
+      uint32_t d = i;
+      if (i >= W2 && i < W2E) d = W2 + ((i - W2) % MLP_H) * MLP_H + (i - W2) / MLP_H;
+      S->model[d] = w.model[i];
+    }
+    c.model = S->model;
+  }
   if (threadIdx.x == 0) { S->sp = 0; S->decisions = 0; }
   __syncthreads();
 }

@@ -66,7 +66,9 @@ __device__ __forceinline__ uint32_t heuristic_proc(uint64_t m, uint64_t parent, 
 }
 
 // Network prediction, one thread.  Returns the masked argmin, or 0xFFFFFFFF
-// if any prediction is not finite.
+// if any prediction is not finite.  W2T: the layer-2 matrix is stored
+// transposed (element (j, i) at i * H + j), the layout of the copy in LDS.
+template <bool W2T = false>
 __device__ __forceinline__ uint32_t mlp_choose(const float* __restrict__ model, const float* feat, uint32_t feas) {
   const float* W1 = model;
   const float* b1 = W1 + MLP_H * MLP_F;
@@ -93,7 +95,7 @@ __device__ __forceinline__ uint32_t mlp_choose(const float* __restrict__ model, 
   for (uint32_t j = 0; j < MLP_H; j++) {
     float a = b2[j];
 #pragma unroll
-    for (uint32_t i = 0; i < MLP_H; i++) a = fmaf(W2[j * MLP_H + i], h1[i], a);
+    for (uint32_t i = 0; i < MLP_H; i++) a = fmaf(W2[W2T ? i * MLP_H + j : j * MLP_H + i], h1[i], a);
     a = a > 0.0f ? a : 0.0f;
 #pragma unroll
     for (uint32_t q = 0; q < MLP_P; q++) y[q] = fmaf(W3[q * MLP_H + j], a, y[q]);
@@ -116,6 +118,7 @@ __device__ __forceinline__ uint32_t mlp_choose(const float* __restrict__ model, 
 // instructions instead of the ~1400 of the one-thread form.  All lanes must
 // be active; every lane returns the same choice (0xFFFFFFFF on a non-finite
 // prediction).
+template <bool W2T = false>
 __device__ __forceinline__ uint32_t mlp_choose_wave(const float* __restrict__ model, const float* feat, uint32_t feas) {
   const float* W1 = model;
   const float* b1 = W1 + MLP_H * MLP_F;
@@ -136,7 +139,7 @@ __device__ __forceinline__ uint32_t mlp_choose_wave(const float* __restrict__ mo
   const float h1 = a > 0.0f ? a : 0.0f;
   float a2 = b2[j];
 #pragma unroll
-  for (uint32_t i = 0; i < MLP_H; i++) a2 = fmaf(W2[j * MLP_H + i], __shfl(h1, (int)i), a2);
+  for (uint32_t i = 0; i < MLP_H; i++) a2 = fmaf(W2[W2T ? i * MLP_H + j : j * MLP_H + i], __shfl(h1, (int)i), a2);
   const float h2 = own && a2 > 0.0f ? a2 : 0.0f;
   uint32_t best = 0xFFFFFFFFu;
   float bv = 0.0f;
@@ -156,6 +159,7 @@ __device__ __forceinline__ uint32_t mlp_choose_wave(const float* __restrict__ mo
 }
 
 // Procedure for a bucket of 32 < m records (single thread).
+template <bool W2T = false>
 __device__ __forceinline__ uint32_t choose_proc(const Plan& p, const float* model, uint64_t m, uint64_t parent,
                                                 uint32_t bit, uint32_t kbits, uint32_t feas) {
   if (feas == 0) return P_LSD;
@@ -165,7 +169,7 @@ __device__ __forceinline__ uint32_t choose_proc(const Plan& p, const float* mode
   } else if (p.sched_mode == RADULS_SCHED_LEARNED && model) {
     float f[MLP_F];
     bucket_features(f, m, parent, bit, kbits, p.rec_bytes, p.key_bytes);
-    uint32_t c = mlp_choose(model, f, feas);
+    uint32_t c = mlp_choose<W2T>(model, f, feas);
     if (c != 0xFFFFFFFFu) return c;
   }
   return heuristic_proc(m, parent, feas);
@@ -173,6 +177,7 @@ __device__ __forceinline__ uint32_t choose_proc(const Plan& p, const float* mode
 
 // choose_proc for a whole wavefront deciding one bucket (all lanes active,
 // same arguments in every lane).
+template <bool W2T = false>
 __device__ __forceinline__ uint32_t choose_proc_wave(const Plan& p, const float* model, uint64_t m, uint64_t parent,
                                                      uint32_t bit, uint32_t kbits, uint32_t feas) {
   if (feas == 0) return P_LSD;
@@ -180,11 +185,11 @@ __device__ __forceinline__ uint32_t choose_proc_wave(const Plan& p, const float*
   if (p.sched_mode == RADULS_SCHED_LEARNED && model) {
     float f[MLP_F];
     bucket_features(f, m, parent, bit, kbits, p.rec_bytes, p.key_bytes);
-    uint32_t c = mlp_choose_wave(model, f, feas);
+    uint32_t c = mlp_choose_wave<W2T>(model, f, feas);
     if (c != 0xFFFFFFFFu) return c;
     return heuristic_proc(m, parent, feas);
   }
-  return choose_proc(p, model, m, parent, bit, kbits, feas);
+  return choose_proc<W2T>(p, model, m, parent, bit, kbits, feas);
 }
 
 }  // namespace rd

@@ -44,9 +44,10 @@ MODEL_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "models", 
 # distribution, and other record shapes.  Held out: new data (other seeds)
 # of the same shapes.
 DISTS = ("uniform", "zipf", "prefix", "mix")
-TRAIN = [(lg, 16, 8, d) for lg in range(22, 28) for d in DISTS] + \
-        [(lg, r, k, d) for lg in (23, 25) for (r, k) in ((8, 8), (32, 8), (32, 16)) for d in ("uniform", "zipf")]
-HOLDOUT = [(lg, 16, 8, d) for lg in (23, 25, 27) for d in DISTS] + [(24, 32, 16, "zipf"), (24, 8, 8, "mix")]
+TRAIN = [(lg, 16, 8, d) for lg in range(22, 31) for d in DISTS] + \
+        [(lg, r, k, d) for lg in (23, 25, 28) for (r, k) in ((8, 8), (32, 8), (32, 16)) for d in ("uniform", "zipf")]
+HOLDOUT = [(lg, 16, 8, d) for lg in (23, 25, 27, 29) for d in DISTS] + \
+          [(24, 32, 16, "zipf"), (24, 8, 8, "mix"), (29, 32, 16, "uniform"), (29, 8, 8, "prefix")]
 
 
 def log(msg):
@@ -209,7 +210,7 @@ def main(argv=None):
     ap.add_argument("--out", required=True)
     ap.add_argument("--steps", type=int, default=6000)
     ap.add_argument("--period", type=int, default=3)
-    ap.add_argument("--compare-log2n", type=int, default=27)
+    ap.add_argument("--compare-log2n", type=int, default=29)
     args = ap.parse_args(argv)
     os.makedirs(args.out, exist_ok=True)
     raduls.set_scheduler(raduls.SCHED_HEURISTIC)
