@@ -82,7 +82,7 @@ typedef struct raduls_tuning {
   uint64_t big_min;           /* big buckets hold more than big_min records (and see big_rule) */
   uint32_t nontemporal;       /* 1: non-temporal stores for scattered output */
   uint32_t big_rule;          /* 0: also more than 2N/(3W) (Sec. 3.2, W = resident workgroups);
-                                 1: big_min alone */
+                                 1: big_min alone (the default, with big_min = 2 tiles) */
   uint32_t job_records;       /* children of a radix pass are grouped into finishing jobs of at
                                  most this many records (0 = the LDS capacity) */
   uint32_t reserved;

@@ -128,7 +128,11 @@ raduls_tuning default_tuning(uint32_t r, uint32_t k, uint64_t n) {
   t.lds_finish_max = 0;
   t.bitonic_max = 0;
   t.workgroups_per_cu = 2;
-  t.big_min = 16ull * t.tile_records;
+  // buckets above two tiles take another multi-workgroup level, whose
+  // children are grouped into finishing jobs (measured faster than a
+  // one-workgroup radix pass on such buckets, for every key distribution)
+  t.big_min = 2ull * t.tile_records;
+  t.big_rule = 1;
   t.nontemporal = 0;
   return t;
 }
@@ -875,7 +879,7 @@ int raduls_tune(uint32_t rec_bytes, uint32_t key_bytes, uint64_t n_hint, void* s
           for (uint32_t rule : {0u, 1u}) {
             raduls_tuning t = base;
             t.tile_records = tile;
-            t.big_min = 16ull * tile;
+            t.big_min = 2ull * tile;
             t.job_records = job;
             t.workgroups_per_cu = wpc;
             t.nontemporal = nt;

@@ -242,6 +242,11 @@ __global__ __launch_bounds__(WG) void k_scan(Plan p, Work w, uint32_t level) {
   constexpr uint32_t RMAX = 1u << DB;
   __shared__ uint64_t off[RMAX];
   __shared__ uint64_t part[WG];
+  // grouping of small children into finishing jobs (digits <= WG)
+  __shared__ uint32_t flag[WG];
+  __shared__ uint32_t stmp[NWAVES];
+  __shared__ uint64_t cst[WG], ccn[WG], gst[WG], gfc[WG];
+  __shared__ uint64_t gend;
   Bucket* list = level_list(p, w, level);
   uint32_t nb = min((uint64_t)w.ctl->nbig[level], p.cap_big);
   const KeyFmt kf = make_keyfmt(p.key_bytes);
@@ -302,6 +307,65 @@ __global__ __launch_bounds__(WG) void k_scan(Plan p, Work w, uint32_t level) {
     }
     __syncthreads();
     uint64_t run = part[threadIdx.x];
+    if (R <= WG) {
+      // Thread t owns digit t.  Children lie consecutively in key order, so
+      // a run of whole children is a valid finishing job: as in the
+      // workgroup radix pass, a child above the job window T is routed on
+      // its own and smaller ones are grouped by the T-window their first
+      // record falls in (a group holds under 2T <= C records).
+      const uint32_t t = threadIdx.x;
+      const uint64_t T = p.job_window;
+      const uint64_t cnt = t < R ? off[t] : 0ull;
+      if (t < R) gh[t] = run;  // digit base, read by the scatter
+      flag[t] = cnt > 0 ? 1u : 0u;
+      const uint32_t nn = block_excl_scan_lds(flag, WG, stmp);
+      if (cnt > 0) { cst[flag[t]] = run; ccn[flag[t]] = cnt; }
+      __syncthreads();
+      uint32_t kb = 0;
+      uint64_t kst = 0, kcnt = 0;
+      if (t < nn) {
+        kst = cst[t];
+        kcnt = ccn[t];
+        kb = 1;
+        if (t > 0) {
+          const uint64_t pst = cst[t - 1], pcnt = ccn[t - 1];
+          kb = (kcnt > T || pcnt > T || kst / T != pst / T) ? 1u : 0u;
+        }
+      }
+      flag[t] = kb;
+      const uint32_t nj = block_excl_scan_lds(flag, WG, stmp);
+      if (kb) { gst[flag[t]] = kst; gfc[flag[t]] = kcnt; }
+      if (t < nn && t + 1 == nn) gend = kst + kcnt;
+      __syncthreads();
+      // a job that a workgroup finishes in LDS goes straight to the job
+      // list (one ticket per bucket); the others are routed one by one
+      Bucket ch{0, 0, 0, 0, 0};
+      bool direct = false;
+      if (t < nj) {
+        const uint64_t js = gst[t], m = (t + 1 < nj ? gst[t + 1] : gend) - js;
+        ch.begin = B.begin + js;
+        ch.count = m;
+        ch.parent = B.count;
+        ch.bit = m == gfc[t] ? B.bit + d : B.bit;
+        ch.flags = (B.flags & BF_TMP) ^ BF_TMP;
+        direct = m > TINY_MAX && m <= p.c_fin && ch.bit < kf.kbits;
+        if (!direct) route_bucket(p, w, level + 1, ch, kf.kbits);
+      }
+      flag[t] = direct ? 1u : 0u;
+      const uint32_t nd = block_excl_scan_lds(flag, WG, stmp);
+      if (nd) {
+        if (t == 0) gend = atomicAdd(&w.ctl->nwg, nd);
+        __syncthreads();
+        if (direct) {
+          const uint64_t i = gend + flag[t];
+          ch.flags |= BF_ROOT;
+          if (i < p.cap_wg) w.wgjobs[i] = ch;
+          else atomicOr(&w.ctl->overflow, 32u);
+        }
+      }
+      __syncthreads();
+      continue;
+    }
     for (uint32_t i = lo; i < hi; i++) {
       uint64_t c = off[i];
       gh[i] = run;  // digit base, read by the scatter
