@@ -244,7 +244,7 @@ __global__ __launch_bounds__(WG) void k_scan(Plan p, Work w, uint32_t level) {
   __shared__ uint64_t part[WG];
   // grouping of small children into finishing jobs (digits <= WG)
   __shared__ uint32_t flag[WG];
-  __shared__ uint32_t stmp[NWAVES];
+  __shared__ uint32_t stmp[NWAVES], smax[NWAVES];
   __shared__ uint64_t cst[WG], ccn[WG], gst[WG], gfc[WG];
   __shared__ uint64_t gend;
   Bucket* list = level_list(p, w, level);
@@ -309,10 +309,10 @@ __global__ __launch_bounds__(WG) void k_scan(Plan p, Work w, uint32_t level) {
     uint64_t run = part[threadIdx.x];
     if (R <= WG) {
       // Thread t owns digit t.  Children lie consecutively in key order, so
-      // a run of whole children is a valid finishing job: as in the
-      // workgroup radix pass, a child above the job window T is routed on
-      // its own and smaller ones are grouped by the T-window their first
-      // record falls in (a group holds under 2T <= C records).
+      // a run of whole children is a valid finishing job.  A child above T
+      // (half the job size J) is routed on its own; smaller ones are grouped
+      // by the window of V = J - (largest of them) records their first
+      // record falls in, so a group holds under V + largest <= J records.
       const uint32_t t = threadIdx.x;
       const uint64_t T = p.job_window;
       const uint64_t cnt = t < R ? off[t] : 0ull;
@@ -320,7 +320,14 @@ __global__ __launch_bounds__(WG) void k_scan(Plan p, Work w, uint32_t level) {
       flag[t] = cnt > 0 ? 1u : 0u;
       const uint32_t nn = block_excl_scan_lds(flag, WG, stmp);
       if (cnt > 0) { cst[flag[t]] = run; ccn[flag[t]] = cnt; }
+      uint32_t mx = cnt <= T ? (uint32_t)cnt : 0u;
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, o));
+      if (lane_id() == 0) smax[t / 64] = mx;
       __syncthreads();
+#pragma unroll
+      for (uint32_t q = 0; q < NWAVES; q++) mx = max(mx, smax[q]);
+      const uint64_t V = 2 * T - max<uint64_t>(mx, 1);
       uint32_t kb = 0;
       uint64_t kst = 0, kcnt = 0;
       if (t < nn) {
@@ -329,7 +336,7 @@ __global__ __launch_bounds__(WG) void k_scan(Plan p, Work w, uint32_t level) {
         kb = 1;
         if (t > 0) {
           const uint64_t pst = cst[t - 1], pcnt = ccn[t - 1];
-          kb = (kcnt > T || pcnt > T || kst / T != pst / T) ? 1u : 0u;
+          kb = (kcnt > T || pcnt > T || kst / V != pst / V) ? 1u : 0u;
         }
       }
       flag[t] = kb;

@@ -23,7 +23,11 @@ constexpr uint32_t RB = 256;          // radix of one-workgroup passes (d_block 
 constexpr uint32_t MAX_ROUNDS = 16;   // LDS finishing capacity <= 16 * WG records
 constexpr uint32_t IPT_BLOCK = 8;     // records per thread in a radix-pass tile
 constexpr uint32_t EMAX = 4;          // records per lane of a wavefront job (at most 256)
-constexpr uint32_t INSERTION_MAX = 32; // insertion sort serves bins of at most 32 keys (Sec. 3.5)
+// The in-LDS radix procedure computes each record's slot within its
+// sub-bucket by counting the smaller composites there, a cost that grows
+// with the sub-bucket; above this size the job is finished by the bitonic
+// network instead.
+constexpr uint32_t RANK_SUB_MAX = 256;
 
 struct SmallShared {
   uint32_t hist[RB];
@@ -732,15 +736,15 @@ __device__ __forceinline__ void wg_finish(Ctx& c, uint64_t begin, uint32_t m, bo
 }
 
 // RADIX on a job that fits LDS: the next radix pass of the bin is made in
-// fast memory and the bins it yields, at most 32 keys each, are sorted
-// directly (paper, Sec. 3.4-3.5, which uses insertion sort there).  The
+// fast memory and the bins it yields are sorted directly (paper, Sec.
+// 3.4-3.5, which uses insertion sort on bins of at most 32 keys there).  The
 // composites (varying key bits << ib | local index) are counted by their top
 // D <= 10 bits and placed in digit order (any order within a digit); then
 // each composite's final slot is its sub-bucket's start plus the number of
 // smaller composites in the sub-bucket -- the insertion sort's result,
 // computed by independent LDS reads instead of a chain of shifts.  The
 // composites are unique, so the result is the stable order.  A sub-bucket
-// above 32 composites (a skewed job: runs of equal keys) makes the workgroup
+// above RANK_SUB_MAX composites (a skewed job: runs of equal keys) makes the workgroup
 // finish the job from the same stage by the bitonic network instead (by LSD
 // if the job exceeds the bitonic capacity), which costs the same whatever
 // the duplicates.  With wide keys (varying bits plus index
@@ -803,7 +807,7 @@ __device__ __forceinline__ void wg_radix_lds(Ctx& c, uint64_t begin, uint32_t m,
     S.bcast = big;  // the same value from every thread
   }
   __syncthreads();
-  if (S.bcast > INSERTION_MAX) {
+  if (S.bcast > RANK_SUB_MAX) {
     wg_sort_staged<RW>(c, begin, m, m <= c.p.bitonic_max ? P_BITONIC : P_LSD, vary);
     return;
   }
