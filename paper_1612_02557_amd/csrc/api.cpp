@@ -207,8 +207,10 @@ Plan make_plan(uint64_t n, uint32_t r, uint32_t k, const raduls_tuning& t, int c
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t ctl, big, tile_start, hist, vary, small, small_ord, tiny, copy, copy_start, stacks, wgjobs, trace_count, total;
-  size_t status_total;  // epoch counter (256 bytes) + look-back words
+  size_t ctl, big, tile_start, hist, vary, tcnt, small, small_ord, tiny, copy, copy_start, stacks, wgjobs, trace_count,
+      total;
+  size_t status_total;  // epoch counter (256 bytes) + tile digit offsets + look-back words
+  size_t cstatus;       // offset of the look-back words in that allocation
 };
 
 Layout layout_of(const Plan& p) {
@@ -221,6 +223,7 @@ Layout layout_of(const Plan& p) {
   L.tile_start = take((size_t)(p.lmax + 1) * (p.cap_big + 1) * 8);
   L.hist = take((size_t)p.cap_big * R * 8);
   L.vary = take((size_t)p.cap_big * 16);
+  L.tcnt = take((size_t)p.max_tiles * R * 4);
   L.small = take((size_t)p.cap_small * sizeof(rd::Bucket));
   L.small_ord = take((size_t)p.cap_small * sizeof(rd::Bucket));
   L.tiny = take((size_t)p.cap_tiny * 8);
@@ -230,7 +233,8 @@ Layout layout_of(const Plan& p) {
   L.wgjobs = take((size_t)p.cap_wg * sizeof(rd::Bucket));
   L.trace_count = take(8);
   L.total = o;
-  L.status_total = 256 + align_up((size_t)p.max_tiles * R * 8);
+  L.cstatus = 256 + align_up((size_t)p.max_tiles * R * 8);
+  L.status_total = L.cstatus + align_up((size_t)(p.max_tiles / rd::TSCAN_CH + 2) * R * 8);
   return L;
 }
 
@@ -303,6 +307,8 @@ int ensure_workspace(DeviceState& s, const Plan& p, Layout& L, hipStream_t strea
   w.hist = (uint64_t*)(s.base + L.hist);
   w.vary = (uint64_t*)(s.base + L.vary);
   w.status = (uint64_t*)(s.status_base + 256);
+  w.cstatus = (uint64_t*)(s.status_base + L.cstatus);
+  w.tcnt = (uint32_t*)(s.base + L.tcnt);
   w.small = (rd::Bucket*)(s.base + L.small);
   w.small_ord = (rd::Bucket*)(s.base + L.small_ord);
   w.tiny = (uint64_t*)(s.base + L.tiny);
@@ -387,6 +393,7 @@ void enqueue_sort(DeviceState& s, const Plan& p, void* records, void* tmp, const
     rd::launch_level_hist(p, s.work, l, records, tmp, st);
     pm.mark(2 + 4 * l);
     rd::launch_level_scan(p, s.work, l, st);
+    rd::launch_tile_scan(p, s.work, l, st);
     pm.mark(3 + 4 * l);
     rd::launch_level_scatter(p, s.work, l, records, tmp, st);
     pm.mark(4 + 4 * l);
@@ -542,6 +549,7 @@ int raduls_partition(const void* in, void* out, uint64_t n, uint32_t rec_bytes, 
   rd::launch_level_prep(p, s.work, 0, st);
   rd::launch_level_hist(p, s.work, 0, const_cast<void*>(in), out, st);
   rd::launch_level_scan(p, s.work, 0, st);
+  rd::launch_tile_scan(p, s.work, 0, st);
   rd::launch_level_scatter(p, s.work, 0, const_cast<void*>(in), out, st);
   HIPCHK(hipGetLastError());
   s.work.counts_out = nullptr;

@@ -157,7 +157,9 @@ __global__ __launch_bounds__(WG) void k_hist(Plan p, Work w, uint32_t level, con
   constexpr uint32_t RMAX = 1u << DB;
   constexpr uint32_t HB = 16;  // keys loaded per thread before they are counted
   constexpr uint32_t HW = RMAX <= 256 ? NWAVES : 1;  // per-wave counters when they are small
-  __shared__ uint32_t sh[HW * RMAX];
+  // two sets of counters: a tile counts into one while the other, holding
+  // the previous tile's counts, is read out and cleared
+  __shared__ uint32_t sh[2 * HW * RMAX];
   __shared__ uint64_t sv[2 * NWAVES];
   const Bucket* list = level_list(p, w, level);
   const uint64_t* start = level_start(p, w, level);
@@ -181,12 +183,18 @@ __global__ __launch_bounds__(WG) void k_hist(Plan p, Work w, uint32_t level, con
     uint32_t mask = (1u << d) - 1u;
     const uint8_t* src = (B.flags & BF_TMP) ? rec1 : rec0;
     Key ref = load_key<RW>(src, B.begin, kf);
-    for (uint32_t i = threadIdx.x; i < HW * RMAX; i += WG) sh[i] = 0;
+    for (uint32_t i = threadIdx.x; i < 2 * HW * RMAX; i += WG) sh[i] = 0;
     __syncthreads();
-    uint32_t* shw = sh + (HW > 1 ? (threadIdx.x / 64) * RMAX : 0);
+    uint32_t par = 0;
     uint64_t vlo = 0, vhi = 0;
     uint64_t bend = B.begin + B.count;
-    for (; t < tend; t++) {
+    constexpr uint32_t KV = (RMAX + WG - 1) / WG;  // digits per thread
+    uint32_t acc[KV];
+#pragma unroll
+    for (uint32_t k = 0; k < KV; k++) acc[k] = 0;
+    for (; t < tend; t++, par ^= 1u) {
+      uint32_t* cur = sh + par * HW * RMAX;
+      uint32_t* shw = cur + (HW > 1 ? (threadIdx.x / 64) * RMAX : 0);
       uint64_t r0 = B.begin + (t - bt0) * p.tile;
       for (uint32_t j0 = 0; j0 < IPT; j0 += HB) {
         Key kk[HB];
@@ -213,17 +221,32 @@ __global__ __launch_bounds__(WG) void k_hist(Plan p, Work w, uint32_t level, con
           }
         }
       }
+      // the tile's counts go to the tile-count array (read by the offset
+      // scan) and into this run's totals, and its counters are cleared
+      // while the next tile counts into the other set
+      __syncthreads();
+      uint32_t* tc = w.tcnt + t * RS;
+#pragma unroll
+      for (uint32_t k = 0; k < KV; k++) {
+        const uint32_t i = threadIdx.x + k * WG;
+        if (i < (1u << d)) {
+          uint32_t c = 0;
+#pragma unroll
+          for (uint32_t q = 0; q < HW; q++) { c += cur[q * RMAX + i]; cur[q * RMAX + i] = 0; }
+          tc[i] = c;
+          acc[k] += c;
+        }
+      }
     }
     vlo = wave_or64(vlo);
     vhi = wave_or64(vhi);
     if (lane == 0) { sv[2 * (threadIdx.x / 64)] = vlo; sv[2 * (threadIdx.x / 64) + 1] = vhi; }
     __syncthreads();
     uint64_t* gh = w.hist + (uint64_t)b * RS;
-    for (uint32_t i = threadIdx.x; i < (1u << d); i += WG) {
-      uint32_t c = 0;
 #pragma unroll
-      for (uint32_t q = 0; q < HW; q++) c += sh[q * RMAX + i];
-      if (c) atomicAdd((unsigned long long*)&gh[i], (unsigned long long)c);
+    for (uint32_t k = 0; k < KV; k++) {
+      const uint32_t i = threadIdx.x + k * WG;
+      if (i < (1u << d) && acc[k]) atomicAdd((unsigned long long*)&gh[i], (unsigned long long)acc[k]);
     }
     if (threadIdx.x == 0) {
       uint64_t a = 0, c = 0;
@@ -392,17 +415,146 @@ __global__ __launch_bounds__(WG) void k_scan(Plan p, Work w, uint32_t level) {
 }
 
 // ---------------------------------------------------------------------------
-// Stable scatter of one level with decoupled look-back.
+// Tile digit offsets of one level: for tile t of bucket b and digit v,
+//   off[t][v] = base[b][v] + (records of digit v in the earlier tiles of b),
+// where base is the digit's start within the bucket (from the scan kernel).
+// The level's tiles are cut into chunks of TSCAN_CH consecutive tiles, which
+// may hold the end of one bucket and the start of others.  A chunk sums, per
+// digit, its tiles of its last bucket and publishes that sum: inclusive when
+// that bucket starts inside the chunk, an aggregate otherwise; a chunk whose
+// first bucket started earlier adds up the words of the chunks before it
+// (decoupled look-back over chunks, tickets taken in order).  Then the
+// scatter reads its tile's offsets instead of waiting on other tiles.
+template <int DB>
+__global__ __launch_bounds__(WG) void k_tile_scan(Plan p, Work w, uint32_t level) {
+  constexpr uint32_t RMAX = 1u << DB;
+  constexpr uint32_t KV = (RMAX + WG - 1) / WG;  // digits per thread
+  constexpr uint32_t CH = TSCAN_CH;
+  static_assert(CH <= WG, "one thread per tile of a chunk");
+  __shared__ uint64_t sticket;
+  __shared__ uint32_t sb;
+  __shared__ uint64_t sst[CH];   // starts of the buckets after the first one (chunk order)
+  const Bucket* list = level_list(p, w, level);
+  const uint64_t* start = level_start(p, w, level);
+  const uint32_t nb = min((uint64_t)w.ctl->nbig[level], p.cap_big);
+  const uint64_t T = w.ctl->ntiles[level];
+  if (nb == 0 || T == 0) return;
+  const uint64_t NC = (T + CH - 1) / CH;
+  const uint32_t RS = 1u << p.d_big;
+  const KeyFmt kf = make_keyfmt(p.key_bytes);
+  const uint64_t epoch = (uint64_t)((w.ctl->epoch + level) & 0x3FFFFFu) << LB_EPOCH_SHIFT;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      const uint64_t c = atomicAdd(&w.ctl->cticket[level], 1u);
+      sticket = c;
+      sb = c < NC ? find_entry(start, nb, c * CH) : 0u;
+    }
+    __syncthreads();
+    const uint64_t c = sticket;
+    const uint32_t b0 = sb;
+    if (c >= NC) break;
+    const uint64_t t0 = c * CH, t1 = min(T, t0 + CH);
+    if (threadIdx.x < CH) {
+      const uint32_t bj = b0 + 1 + threadIdx.x;
+      sst[threadIdx.x] = bj < nb ? start[bj] : ~0ull;
+    }
+    __syncthreads();
+    // buckets b0 .. bl hold the chunk's tiles; bucket b0 + 1 + j starts at sst[j]
+    uint32_t nin = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < CH; j++) nin += sst[j] < t1 ? 1u : 0u;
+    const uint32_t bl = b0 + nin;
+    const bool cont = start[b0] < t0;          // the first bucket started before this chunk
+    const bool lin = nin > 0 || !cont;         // the last bucket starts inside it (else bl == b0)
+    const uint64_t ts = nin > 0 ? sst[nin - 1] : t0;   // first tile of the last bucket here
+    // digits of the first and the last bucket (a bucket's tile counts hold
+    // only its own digits)
+    const uint32_t rf = 1u << min(p.d_big, kf.kbits - list[b0].bit);
+    const uint32_t rl = 1u << min(p.d_big, kf.kbits - list[bl].bit);
+#pragma unroll 1
+    for (uint32_t k = 0; k < KV; k++) {
+      const uint32_t v = threadIdx.x + k * WG;
+      if (v >= RS) break;
+      uint32_t cnt[CH];
+#pragma unroll
+      for (uint32_t u = 0; u < CH; u++) cnt[u] = t0 + u < t1 ? w.tcnt[(t0 + u) * RS + v] : 0u;
+      // 1. the last bucket's sum over this chunk, published at once
+      uint64_t agg = 0;
+#pragma unroll
+      for (uint32_t u = 0; u < CH; u++) agg += t0 + u >= ts ? cnt[u] : 0u;
+      uint64_t* cs = w.cstatus + c * RS;
+      if (v < rl) atomic_store_agent(&cs[v], epoch | (lin ? LB_INC : LB_AGG) | agg);
+      // 2. the carry into the first bucket: the sums of the earlier chunks
+      //    back to one that holds that bucket's start
+      uint64_t run = 0;
+      if (cont && v < rf) {
+        // the words of LW chunks are read at once, then used in order up to
+        // the first inclusive one (or the first that is not ready yet)
+        constexpr uint32_t LW = 16;
+        uint64_t jc = c;  // the window is chunks jc-1, jc-2, ...
+        uint32_t spins = 0;
+        for (;;) {
+          uint64_t sw[LW];
+#pragma unroll
+          for (uint32_t i = 0; i < LW; i++)
+            sw[i] = jc > i ? atomic_load_agent(&w.cstatus[(jc - 1 - i) * RS + v]) : (epoch | LB_INC);
+          bool done = false, stall = false;
+          uint32_t used = 0;
+#pragma unroll
+          for (uint32_t i = 0; i < LW; i++) {
+            if (done || stall) continue;
+            const uint64_t s = sw[i];
+            if ((s >> LB_EPOCH_SHIFT) != (epoch >> LB_EPOCH_SHIFT) || (s & LB_FLAGS) == 0) { stall = true; continue; }
+            run += s & LB_VAL;
+            used = i + 1;
+            done = (s & LB_FLAGS) == LB_INC;
+          }
+          jc -= used;
+          if (done) break;
+          if (stall) {
+            if (++spins > LB_SPIN_LIMIT) { atomicOr(&w.ctl->error, 2u); break; }
+            __builtin_amdgcn_s_sleep(1);
+          }
+        }
+        // a chunk inside one bucket can now publish its inclusive sum too
+        if (!lin) atomic_store_agent(&cs[v], epoch | LB_INC | (run + agg));
+      }
+      // 3. the tiles' offsets
+      uint32_t b = b0, nxt = 0;
+      uint32_t r = rf;
+      uint64_t base = v < r ? w.hist[(uint64_t)b * RS + v] : 0ull;
+#pragma unroll
+      for (uint32_t u = 0; u < CH; u++) {
+        const uint64_t t = t0 + u;
+        if (t < t1) {
+          if (nxt < nin && sst[nxt] == t) {
+            b++;
+            nxt++;
+            run = 0;
+            r = 1u << min(p.d_big, kf.kbits - list[b].bit);
+            base = v < r ? w.hist[(uint64_t)b * RS + v] : 0ull;
+          }
+          if (v < r) w.status[t * RS + v] = base + run;
+          run += cnt[u];
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Stable scatter of one level.
 //
-// A tile is `tile` consecutive records of one bucket; tiles are claimed in
-// order through an atomic ticket, so every tile a workgroup waits for
-// belongs to a workgroup that started earlier.  Within a tile, wave q owns
-// records [q*tile/4, (q+1)*tile/4) and takes them 64 at a time; a record's
-// rank among equal digits is (count in earlier waves) + (count in earlier
-// rounds of its wave) + (lanes of its round with the same digit below it), so
-// the tile keeps input order within each digit.  The tile publishes its
-// per-digit counts, adds up its predecessors' counts by look-back, stages the
-// records in LDS ordered by digit, and writes each digit's run contiguously.
+// A tile is `tile` consecutive records of one bucket (the same tiles the
+// histogram kernel counted); workgroups take tiles through an atomic ticket.
+// Within a tile, wave q owns records [q*tile/4, (q+1)*tile/4) and takes them
+// 64 at a time; a record's rank among equal digits is (count in earlier
+// waves) + (count in earlier rounds of its wave) + (lanes of its round with
+// the same digit below it), so the tile keeps input order within each digit.
+// The tile stages its records in LDS ordered by digit and writes each
+// digit's run contiguously at the offset the tile-offset scan computed for
+// it, so no tile waits for another.
 template <int RW, int DB>
 __global__ __launch_bounds__(WG) void k_scatter(Plan p, Work w, uint32_t level, const uint8_t* rec0,
                                                 uint8_t* rec0w, const uint8_t* rec1, uint8_t* rec1w) {
@@ -411,7 +563,6 @@ __global__ __launch_bounds__(WG) void k_scatter(Plan p, Work w, uint32_t level, 
   extern __shared__ __align__(16) uint32_t stage[];
   __shared__ uint32_t wcnt[NWAVES * RMAX];
   __shared__ uint32_t toff[RMAX + 1];
-  __shared__ uint32_t tcnt[RMAX];
   __shared__ uint64_t gbase[RMAX];
   __shared__ uint32_t sscan[NWAVES + 1];
   __shared__ uint64_t sticket;
@@ -428,7 +579,6 @@ __global__ __launch_bounds__(WG) void k_scatter(Plan p, Work w, uint32_t level, 
   const uint32_t RS = 1u << p.d_big;
   const uint32_t IPT = p.tile / WG;
   const uint32_t per_wave = p.tile / NWAVES;
-  const uint64_t epoch = (uint64_t)((w.ctl->epoch + level) & 0x3FFFFFu) << LB_EPOCH_SHIFT;
   const bool nt = p.nontemporal != 0;
 
   // The next tile is claimed, and the per-wave counters cleared, just before
@@ -454,6 +604,9 @@ __global__ __launch_bounds__(WG) void k_scatter(Plan p, Work w, uint32_t level, 
     }
     uint64_t ti = ticket - start[b];
     uint64_t r0 = B.begin + ti * p.tile;
+    // this tile's digit offsets, loaded early (used after the staging)
+    const uint64_t tofs = threadIdx.x < (1u << min(p.d_big, kf.kbits - B.bit)) && threadIdx.x < RS
+                              ? w.status[ticket * RS + threadIdx.x] : 0ull;
     uint64_t bend = B.begin + B.count;
     uint32_t cnt = (uint32_t)min((uint64_t)p.tile, bend - r0);
     uint32_t d = min(p.d_big, kf.kbits - B.bit);
@@ -489,17 +642,13 @@ __global__ __launch_bounds__(WG) void k_scatter(Plan p, Work w, uint32_t level, 
     for (uint32_t j = 0; j < IPT_MAX; j++)
       if (j < IPT) rk[j] = rank_finish(rp[j]);
     __syncthreads();
-    // the tile's digit counts are known: publish them for the tiles after
-    // it as early as possible (the first tile of a bucket publishes an
-    // inclusive word at once)
-    uint64_t* st = w.status + ticket * RS;
+    // the tile's digit counts: per-wave bases, and the tile's own digit
+    // starts (an exclusive scan) for staging
     for (uint32_t v = threadIdx.x; v < R; v += WG) {
       uint32_t s = 0;
 #pragma unroll
       for (int q = 0; q < NWAVES; q++) { uint32_t c = wcnt[q * RMAX + v]; wcnt[q * RMAX + v] = s; s += c; }
-      tcnt[v] = s;
       toff[v] = s;
-      atomic_store_agent(&st[v], epoch | (ti == 0 ? LB_INC : LB_AGG) | (uint64_t)s);
     }
     __syncthreads();
     block_excl_scan_lds(toff, R, sscan);
@@ -514,29 +663,12 @@ __global__ __launch_bounds__(WG) void k_scatter(Plan p, Work w, uint32_t level, 
         }
       }
     }
-    // decoupled look-back, one digit per thread
-    const uint64_t* dbase = w.hist + (uint64_t)b * RS;
-    for (uint32_t v = threadIdx.x; v < R; v += WG) {
-      uint64_t c = tcnt[v];
-      uint64_t excl = 0;
-      if (ti != 0) {
-        uint64_t j = ticket - 1;
-        uint32_t spins = 0;
-        for (;;) {
-          uint64_t s = atomic_load_agent(&w.status[j * RS + v]);
-          bool ready = (s >> LB_EPOCH_SHIFT) == (epoch >> LB_EPOCH_SHIFT) && (s & LB_FLAGS) != 0;
-          if (!ready) {
-            if (++spins > LB_SPIN_LIMIT) { atomicOr(&w.ctl->error, 2u); break; }
-            __builtin_amdgcn_s_sleep(1);
-            continue;
-          }
-          excl += s & LB_VAL;
-          if ((s & LB_FLAGS) == LB_INC) break;
-          j--;
-        }
-        atomic_store_agent(&st[v], epoch | LB_INC | (excl + c));
-      }
-      gbase[v] = B.begin + dbase[v] + excl - toff[v];
+    // where each digit's run of this tile goes (from the offset scan)
+    if (R <= WG) {
+      if (threadIdx.x < R) gbase[threadIdx.x] = B.begin + tofs - toff[threadIdx.x];
+    } else {
+      const uint64_t* to = w.status + ticket * RS;
+      for (uint32_t v = threadIdx.x; v < R; v += WG) gbase[v] = B.begin + to[v] - toff[v];
     }
     __syncthreads();
     for (uint32_t q = threadIdx.x; q < cnt; q += WG) {
@@ -677,8 +809,15 @@ void launch_level_hist(const Plan& p, const Work& w, uint32_t level, void* recor
 }
 
 void launch_level_scan(const Plan& p, const Work& w, uint32_t level, hipStream_t s) {
-  if (p.d_big > 8) k_scan<11><<<p.grid_clear, WG, 0, s>>>(p, w, level);
-  else k_scan<8><<<p.grid_clear, WG, 0, s>>>(p, w, level);
+  // one workgroup per bucket at a time; latency-bound, so a large grid
+  const uint32_t g = 4 * p.grid_clear;
+  if (p.d_big > 8) k_scan<11><<<g, WG, 0, s>>>(p, w, level);
+  else k_scan<8><<<g, WG, 0, s>>>(p, w, level);
+}
+
+void launch_tile_scan(const Plan& p, const Work& w, uint32_t level, hipStream_t s) {
+  if (p.d_big > 8) k_tile_scan<11><<<p.grid_clear, WG, 0, s>>>(p, w, level);
+  else k_tile_scan<8><<<p.grid_clear, WG, 0, s>>>(p, w, level);
 }
 
 void launch_level_scatter(const Plan& p, const Work& w, uint32_t level, void* records, void* tmp, hipStream_t s) {

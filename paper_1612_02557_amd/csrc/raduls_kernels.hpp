@@ -14,6 +14,7 @@ void launch_seed_segments(const Plan& p, const Work& w, const uint64_t* off, uin
 void launch_level_prep(const Plan& p, const Work& w, uint32_t level, hipStream_t s);
 void launch_level_hist(const Plan& p, const Work& w, uint32_t level, void* records, void* tmp, hipStream_t s);
 void launch_level_scan(const Plan& p, const Work& w, uint32_t level, hipStream_t s);
+void launch_tile_scan(const Plan& p, const Work& w, uint32_t level, hipStream_t s);
 void launch_level_scatter(const Plan& p, const Work& w, uint32_t level, void* records, void* tmp, hipStream_t s);
 void launch_order_small(const Plan& p, const Work& w, hipStream_t s);
 void launch_small(const Plan& p, const Work& w, void* records, void* tmp, hipStream_t s);

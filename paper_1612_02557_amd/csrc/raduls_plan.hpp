@@ -19,6 +19,7 @@ constexpr uint32_t BF_SKIP = 2u;
 constexpr uint32_t BF_ROOT = 4u;  // deferred job that is a queued bucket (one more radix pass allowed)
 
 constexpr uint32_t LMAX = 20;        // multi-workgroup levels a plan may launch
+constexpr uint32_t TSCAN_CH = 32;    // tiles per chunk of the tile-offset scan
 constexpr uint32_t TINY_MAX = 32;    // buckets this small go to one wavefront (Sec. 3.5: N <= 32)
 constexpr uint32_t SMALL_LDS_BYTES = 80 * 1024;  // dynamic LDS of the single-workgroup kernel
 constexpr uint32_t NCLASS = 40;      // size classes of the queued buckets (floor(log2(count)))
@@ -28,6 +29,7 @@ constexpr uint32_t NCLASS = 40;      // size classes of the queued buckets (floo
 struct Ctl {
   uint32_t nbig[LMAX + 1];     // entries of each multi-workgroup list
   uint32_t ticket[LMAX + 1];   // tile tickets of each level's scatter
+  uint32_t cticket[LMAX + 1];  // chunk tickets of each level's tile-offset scan
   uint64_t ntiles[LMAX + 1];   // tiles of each list (set by the prefix kernel)
   uint32_t nsmall;             // queued single-workgroup buckets
   uint32_t ntiny;              // queued tiny buckets
@@ -87,7 +89,9 @@ struct Work {
   uint64_t* tile_start;       // (LMAX + 1) x (cap_big + 1)
   uint64_t* hist;             // cap_big x 2^d_big (per level, reused)
   uint64_t* vary;             // cap_big x 2 (OR of key XOR reference key)
-  uint64_t* status;           // look-back words, max_tiles x 2^d_big
+  uint64_t* status;           // tile digit offsets, max_tiles x 2^d_big, then the chunk look-back words
+  uint32_t* tcnt;             // tile digit counts, max_tiles x 2^d_big
+  uint64_t* cstatus;          // look-back words of the tile-offset scan, (max_tiles / TSCAN_CH + 2) x 2^d_big
   Bucket* small;       // cap_small
   Bucket* small_ord;   // cap_small, ordered largest class first
   uint64_t* tiny;             // cap_tiny packed tiny buckets
