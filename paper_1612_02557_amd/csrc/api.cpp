@@ -207,7 +207,7 @@ Plan make_plan(uint64_t n, uint32_t r, uint32_t k, const raduls_tuning& t, int c
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t ctl, big, tile_start, hist, vary, tcnt, small, small_ord, tiny, copy, copy_start, stacks, wgjobs, trace_count,
+  size_t ctl, big, tile_start, hist, vary, tcnt, tbucket, small, small_ord, tiny, copy, copy_start, stacks, wgjobs, trace_count,
       total;
   size_t status_total;  // epoch counter (256 bytes) + tile digit offsets + look-back words
   size_t cstatus;       // offset of the look-back words in that allocation
@@ -224,6 +224,7 @@ Layout layout_of(const Plan& p) {
   L.hist = take((size_t)p.cap_big * R * 8);
   L.vary = take((size_t)p.cap_big * 16);
   L.tcnt = take((size_t)p.max_tiles * R * 4);
+  L.tbucket = take((size_t)p.max_tiles * 4);
   L.small = take((size_t)p.cap_small * sizeof(rd::Bucket));
   L.small_ord = take((size_t)p.cap_small * sizeof(rd::Bucket));
   L.tiny = take((size_t)p.cap_tiny * 8);
@@ -309,6 +310,7 @@ int ensure_workspace(DeviceState& s, const Plan& p, Layout& L, hipStream_t strea
   w.status = (uint64_t*)(s.status_base + 256);
   w.cstatus = (uint64_t*)(s.status_base + L.cstatus);
   w.tcnt = (uint32_t*)(s.base + L.tcnt);
+  w.tbucket = (uint32_t*)(s.base + L.tbucket);
   w.small = (rd::Bucket*)(s.base + L.small);
   w.small_ord = (rd::Bucket*)(s.base + L.small_ord);
   w.tiny = (uint64_t*)(s.base + L.tiny);

@@ -260,6 +260,117 @@ __global__ __launch_bounds__(WG) void k_hist(Plan p, Work w, uint32_t level, con
 
 // ---------------------------------------------------------------------------
 // Per-bucket scan and classification.  One workgroup per list entry.
+// Per-level histogram for digits of at most 8 bits, one wavefront per
+// tile: wave q of a workgroup takes tiles ta + q, ta + q + NWAVES, ... of the
+// workgroup's range, counts a tile's digits in its own LDS counters, writes
+// them out as the tile's counts and adds them to per-lane totals, which go to
+// the bucket's histogram (and the key-bit OR to its varying mask) when the
+// wave moves on to another bucket.  No workgroup barrier, so a wave's loads
+// keep streaming from one tile into the next.
+template <int RW>
+__global__ __launch_bounds__(WG) void k_hist_wave(Plan p, Work w, uint32_t level, const uint8_t* rec0,
+                                                  const uint8_t* rec1) {
+  constexpr uint32_t RMAX = 256;
+  constexpr uint32_t HB = 16;          // keys loaded per lane before they are counted
+  constexpr uint32_t DL = RMAX / 64;   // digits per lane
+  __shared__ uint32_t sh[NWAVES * RMAX];
+  const Bucket* list = level_list(p, w, level);
+  const uint64_t* start = level_start(p, w, level);
+  const uint32_t nb = min((uint64_t)w.ctl->nbig[level], p.cap_big);
+  const uint64_t T = w.ctl->ntiles[level];
+  if (nb == 0 || T == 0) return;
+  const uint64_t per = (T + gridDim.x - 1) / gridDim.x;
+  const uint64_t ta = blockIdx.x * per, tz = min(T, ta + per);
+  const KeyFmt kf = make_keyfmt(p.key_bytes);
+  const uint32_t lane = lane_id();
+  const uint32_t wave = threadIdx.x / 64;
+  const uint32_t RS = 1u << p.d_big;
+  const uint32_t IPW = p.tile / 64;    // records per lane of a tile
+  uint32_t* cw = sh + wave * RMAX;
+  for (uint32_t v = threadIdx.x; v < NWAVES * RMAX; v += WG) sh[v] = 0;
+  __syncthreads();
+  constexpr uint32_t NONE = 0xFFFFFFFFu;
+  uint32_t b = NONE, d = 0, shift = 0, mask = 0;
+  uint64_t bt0 = 0, bnext = 0, bbegin = 0, bend = 0;
+  const uint8_t* src = rec0;
+  Key ref{0, 0};
+  uint64_t vlo = 0, vhi = 0;
+  uint32_t acc[DL];
+  auto flush = [&]() {
+    uint64_t* gh = w.hist + (uint64_t)b * RS;
+#pragma unroll
+    for (uint32_t k = 0; k < DL; k++) {
+      const uint32_t v = lane + 64 * k;
+      if (v < (1u << d) && acc[k]) atomicAdd((unsigned long long*)&gh[v], (unsigned long long)acc[k]);
+    }
+    const uint64_t a = wave_or64(vlo), c = wave_or64(vhi);
+    if (lane == 0) {
+      if (a) atomicOr((unsigned long long*)&w.vary[2 * b], (unsigned long long)a);
+      if (c) atomicOr((unsigned long long*)&w.vary[2 * b + 1], (unsigned long long)c);
+    }
+  };
+  for (uint64_t t = ta + wave; t < tz; t += NWAVES) {
+    if (b == NONE || t >= bnext) {
+      if (b != NONE) flush();
+      if (b == NONE) b = find_entry(start, nb, t);
+      else while (start[b + 1] <= t) b++;
+      const Bucket B = list[b];
+      bt0 = start[b];
+      bnext = start[b + 1];
+      bbegin = B.begin;
+      bend = B.begin + B.count;
+      d = min(p.d_big, kf.kbits - B.bit);
+      shift = kf.kbits - B.bit - d;
+      mask = (1u << d) - 1u;
+      src = (B.flags & BF_TMP) ? rec1 : rec0;
+      ref = load_key<RW>(src, B.begin, kf);
+      vlo = vhi = 0;
+#pragma unroll
+      for (uint32_t k = 0; k < DL; k++) acc[k] = 0;
+    }
+    const uint64_t r0 = bbegin + (t - bt0) * p.tile;
+    for (uint32_t j0 = 0; j0 < IPW; j0 += HB) {
+      Key kk[HB];
+#pragma unroll
+      for (uint32_t u = 0; u < HB; u++) {
+        const uint64_t i = r0 + (uint64_t)(j0 + u) * 64 + lane;
+        kk[u] = (j0 + u < IPW && i < bend) ? load_key<RW>(src, i, kf) : ref;
+      }
+#pragma unroll
+      for (uint32_t u = 0; u < HB; u++) {
+        const uint64_t i = r0 + (uint64_t)(j0 + u) * 64 + lane;
+        const bool valid = j0 + u < IPW && i < bend;
+        vlo |= kk[u].lo ^ ref.lo;
+        vhi |= kk[u].hi ^ ref.hi;
+        const uint32_t v = key_digit(kk[u], shift, mask, kf);
+        const uint64_t active = __ballot(valid);
+        const uint32_t v0 = __shfl(v, 0);
+        if (active == ~0ull && __ballot(v == v0) == ~0ull) {
+          if (lane == 0) atomicAdd(&cw[v0], 64u);
+        } else if (valid) {
+          atomicAdd(&cw[v], 1u);
+        }
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    uint32_t* tc = w.tcnt + t * RS;
+#pragma unroll
+    for (uint32_t k = 0; k < DL; k++) {
+      const uint32_t v = lane + 64 * k;
+      if (v < (1u << d)) {
+        const uint32_t c = cw[v];
+        cw[v] = 0;
+        tc[v] = c;
+        acc[k] += c;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  }
+  if (b != NONE) flush();
+}
+
 template <int DB>
 __global__ __launch_bounds__(WG) void k_scan(Plan p, Work w, uint32_t level) {
   constexpr uint32_t RMAX = 1u << DB;
@@ -535,6 +646,7 @@ __global__ __launch_bounds__(WG) void k_tile_scan(Plan p, Work w, uint32_t level
             base = v < r ? w.hist[(uint64_t)b * RS + v] : 0ull;
           }
           if (v < r) w.status[t * RS + v] = base + run;
+          if (k == 0 && threadIdx.x == 0) w.tbucket[t] = b;
           run += cnt[u];
         }
       }
@@ -586,7 +698,7 @@ __global__ __launch_bounds__(WG) void k_scatter(Plan p, Work w, uint32_t level, 
   auto claim = [&]() {
     uint64_t tk = atomicAdd(&w.ctl->ticket[level], 1u);
     sticket = tk;
-    sb = tk < T ? find_entry(start, nb, tk) : 0;
+    sb = tk < T ? w.tbucket[tk] : 0;
   };
   for (uint32_t i = threadIdx.x; i < NWAVES * RMAX; i += WG) wcnt[i] = 0;
   if (threadIdx.x == 0) claim();
@@ -799,7 +911,7 @@ void launch_level_hist(const Plan& p, const Work& w, uint32_t level, void* recor
   const uint8_t* r1 = (const uint8_t*)tmp;
   switch (p.rw * 2 + (p.d_big > 8 ? 1 : 0)) {
 #define RD_CASE(n)                                                                         \
-  case 2 * n: k_hist<n, 8><<<p.grid_hist, WG, 0, s>>>(p, w, level, r0, r1); break;       \
+  case 2 * n: k_hist_wave<n><<<p.grid_hist, WG, 0, s>>>(p, w, level, r0, r1); break;     \
   case 2 * n + 1: k_hist<n, 11><<<p.grid_hist, WG, 0, s>>>(p, w, level, r0, r1); break;
     RD_CASE(1) RD_CASE(2) RD_CASE(3) RD_CASE(4) RD_CASE(5) RD_CASE(6) RD_CASE(7) RD_CASE(8)
     RD_CASE(9) RD_CASE(10) RD_CASE(11) RD_CASE(12) RD_CASE(13) RD_CASE(14) RD_CASE(15) RD_CASE(16)

@@ -91,6 +91,7 @@ struct Work {
   uint64_t* vary;             // cap_big x 2 (OR of key XOR reference key)
   uint64_t* status;           // tile digit offsets, max_tiles x 2^d_big, then the chunk look-back words
   uint32_t* tcnt;             // tile digit counts, max_tiles x 2^d_big
+  uint32_t* tbucket;          // list entry of each tile of the level (set by the offset scan)
   uint64_t* cstatus;          // look-back words of the tile-offset scan, (max_tiles / TSCAN_CH + 2) x 2^d_big
   Bucket* small;       // cap_small
   Bucket* small_ord;   // cap_small, ordered largest class first
