@@ -206,7 +206,7 @@ def main():
     ap.add_argument("--dist", default="uniform")
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-sample-log2", type=int, default=26)
+    ap.add_argument("--cpu-sample-log2", type=int, default=28)
     ap.add_argument("--phases", type=int, default=1, help="1: per-phase events during the timed steps")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-scheduler leg")
     ap.add_argument("--tuning", default="", help="tuning overrides, e.g. big_min=8192,workgroups_per_cu=3")

@@ -24,7 +24,7 @@
  * unless stated otherwise.
  *
  * Ownership: the caller owns every buffer it passes.  The library owns a
- * per-device workspace (bucket lists, histograms, look-back status, queues)
+ * per-device workspace (bucket lists, histograms, tile offsets, queues)
  * that grows on demand and is freed by raduls_release().  Calls on different
  * streams of one device serialise on that workspace (the library orders them
  * with an event); calls from several host threads are serialised by a mutex.
@@ -133,7 +133,7 @@ int raduls_sort_segmented(void* records, void* tmp, const uint64_t* seg_offsets,
  * 1 <= bits <= 11 and shift < 8*key_bytes: `out` (device) receives the
  * records of `in` (device) ordered by that digit, equal digits in input
  * order.  This is one MSD level on a single bucket, run by the same
- * multi-workgroup histogram, look-back scan and scatter kernels the sort
+ * multi-workgroup histogram, offset-scan and scatter kernels the sort
  * uses.  If `counts` (device, 2^bits uint64) is not NULL it receives the
  * histogram. */
 int raduls_partition(const void* in, void* out, uint64_t n, uint32_t rec_bytes, uint32_t key_bytes,
