@@ -182,7 +182,7 @@ Plan make_plan(uint64_t n, uint32_t r, uint32_t k, const raduls_tuning& t, int c
   p.nontemporal = t.nontemporal;
   p.grid_small = cus * t.workgroups_per_cu;
   p.grid_scatter = cus * 2;
-  p.grid_hist = cus * 4;
+  p.grid_hist = cus * 8;
   p.grid_clear = cus * 4;
   uint64_t W = p.grid_small;
   p.t_big = std::max<uint64_t>(t.big_min, (uint64_t)p.c_fin);

@@ -433,14 +433,19 @@ __global__ __launch_bounds__(WG) void k_scan(Plan p, Work w, uint32_t level) {
     uint32_t lo = min(R, threadIdx.x * per), hi = min(R, lo + per);
     uint64_t s = 0;
     for (uint32_t i = lo; i < hi; i++) { off[i] = gh[i]; s += off[i]; }
-    part[threadIdx.x] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      uint64_t run = 0;
-      for (int i = 0; i < WG; i++) { uint64_t c = part[i]; part[i] = run; run += c; }
+    // exclusive scan of the threads' sums: within each wavefront by
+    // shuffles, then across the wavefronts through LDS
+    uint64_t run = s;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint64_t y = __shfl_up((unsigned long long)run, o);
+      if ((int)lane_id() >= o) run += y;
     }
+    if (lane_id() == 63) part[threadIdx.x / 64] = run;
     __syncthreads();
-    uint64_t run = part[threadIdx.x];
+#pragma unroll
+    for (uint32_t q = 0; q < NWAVES; q++) run += q < threadIdx.x / 64 ? part[q] : 0ull;
+    run -= s;
     if (R <= WG) {
       // Thread t owns digit t.  Children lie consecutively in key order, so
       // a run of whole children is a valid finishing job.  A child above T
