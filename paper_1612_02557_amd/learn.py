@@ -45,7 +45,7 @@ MODEL_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "models", 
 # of the same shapes.
 DISTS = ("uniform", "zipf", "prefix", "mix")
 TRAIN = [(lg, 16, 8, d) for lg in range(22, 31) for d in DISTS] + \
-        [(lg, r, k, d) for lg in (23, 25, 28) for (r, k) in ((8, 8), (32, 8), (32, 16)) for d in ("uniform", "zipf")]
+        [(lg, r, k, d) for lg in (23, 25, 28) for (r, k) in ((8, 8), (32, 8), (32, 16)) for d in ("uniform", "zipf", "prefix")]
 HOLDOUT = [(lg, 16, 8, d) for lg in (23, 25, 27, 29) for d in DISTS] + \
           [(24, 32, 16, "zipf"), (24, 8, 8, "mix"), (29, 32, 16, "uniform"), (29, 8, 8, "prefix")]
 
