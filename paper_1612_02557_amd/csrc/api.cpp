@@ -201,7 +201,20 @@ Plan make_plan(uint64_t n, uint32_t r, uint32_t k, const raduls_tuning& t, int c
   p.sched_mode = g_sched_mode;
   p.forced_proc = g_forced;
   p.segmented = segs ? 1 : 0;
+  // a look-back wait gives up after this many polls (about 2 ms); the
+  // environment can lower it to exercise the give-up path in tests
+  p.spin_limit = 1u << 16;
+  if (const char* e = getenv("RADULS_TEST_SPIN_LIMIT")) p.spin_limit = (uint32_t)strtoul(e, nullptr, 10);
   return p;
+}
+
+// The multi-workgroup levels must be able to resolve every key bit: a
+// digit width that needs more than LMAX levels for this key is refused.
+int check_levels(uint32_t key_bytes, const raduls_tuning& t) {
+  const uint32_t kb = 8 * key_bytes;
+  if ((kb + t.big_digit_bits - 1) / t.big_digit_bits + 1 > rd::LMAX)
+    return fail(RADULS_EUNSUPPORTED, "big_digit_bits too small for this key size (more levels than the plan holds)");
+  return RADULS_OK;
 }
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -437,16 +450,20 @@ int raduls_sort(void* records, void* tmp, uint64_t n, uint32_t rec_bytes, uint32
   if (((uintptr_t)records & 15) || ((uintptr_t)tmp & 15)) return fail(RADULS_EINVAL, "buffers must be 16-byte aligned");
   if (overlap(records, tmp, n * rec_bytes)) return fail(RADULS_EINVAL, "records and tmp overlap");
   std::lock_guard<std::mutex> lock(g_mu);
+  raduls_tuning t = current_tuning(rec_bytes, key_bytes, n);
+  rc = check_levels(key_bytes, t);
+  if (rc) return rc;
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
   DeviceState& s = state_for(dev);
   hipStream_t st = (hipStream_t)stream;
-  raduls_tuning t = current_tuning(rec_bytes, key_bytes, n);
   Plan p = make_plan(n, rec_bytes, key_bytes, t, s.cu_count, 0);
   Layout L;
-  rc = prepare(s, p, L, st);
-  if (rc) return rc;
+  // ordered after the previous call before anything (a workspace reset
+  // included) touches the workspace on this stream
   rc = order_after_previous(s, st);
+  if (rc) return rc;
+  rc = prepare(s, p, L, st);
   if (rc) return rc;
   if (g_timing) {
     if (!s.t0) { HIPCHK(hipEventCreate(&s.t0)); HIPCHK(hipEventCreate(&s.t1)); }
@@ -473,16 +490,18 @@ int raduls_sort_segmented(void* records, void* tmp, const uint64_t* seg_offsets,
   if (((uintptr_t)seg_offsets & 7)) return fail(RADULS_EINVAL, "seg_offsets must be 8-byte aligned");
   if (overlap(records, tmp, total_records * rec_bytes)) return fail(RADULS_EINVAL, "records and tmp overlap");
   std::lock_guard<std::mutex> lock(g_mu);
+  raduls_tuning t = current_tuning(rec_bytes, key_bytes, total_records);
+  rc = check_levels(key_bytes, t);
+  if (rc) return rc;
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
   DeviceState& s = state_for(dev);
   hipStream_t st = (hipStream_t)stream;
-  raduls_tuning t = current_tuning(rec_bytes, key_bytes, total_records);
   Plan p = make_plan(total_records, rec_bytes, key_bytes, t, s.cu_count, num_segs);
   Layout L;
-  rc = prepare(s, p, L, st);
-  if (rc) return rc;
   rc = order_after_previous(s, st);
+  if (rc) return rc;
+  rc = prepare(s, p, L, st);
   if (rc) return rc;
   if (!s.capture_stream) HIPCHK(hipStreamCreateWithFlags(&s.capture_stream, hipStreamNonBlocking));
   GraphKey key{records, tmp, seg_offsets, num_segs, total_records, rec_bytes, key_bytes,
@@ -540,9 +559,9 @@ int raduls_partition(const void* in, void* out, uint64_t n, uint32_t rec_bytes, 
   p.cap_big = 2;
   p.max_tiles = n / p.tile + 4;
   Layout L;
-  rc = prepare(s, p, L, st);
-  if (rc) return rc;
   rc = order_after_previous(s, st);
+  if (rc) return rc;
+  rc = prepare(s, p, L, st);
   if (rc) return rc;
   s.work.counts_out = counts;
   p.partition_bit = 8 * key_bytes - shift - bits;

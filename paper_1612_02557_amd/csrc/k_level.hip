@@ -16,7 +16,6 @@
 
 namespace rd {
 
-constexpr uint32_t LB_SPIN_LIMIT = 1u << 16;  // look-back waits this many polls at most
 
 __device__ __forceinline__ Bucket* level_list(const Plan& p, const Work& w, uint32_t level) {
   return w.big + (uint64_t)level * p.cap_big;
@@ -609,7 +608,12 @@ __global__ __launch_bounds__(WG) void k_tile_scan(Plan p, Work w, uint32_t level
         constexpr uint32_t LW = 16;
         uint64_t jc = c;  // the window is chunks jc-1, jc-2, ...
         uint32_t spins = 0;
+        bool gave_up = false;
         for (;;) {
+          // the wait is bounded: past the plan's poll limit the chunk gives
+          // up, flags the error and publishes nothing more, so every wave
+          // exits and the scatter of this level is skipped
+          if (spins >= p.spin_limit) { atomicOr(&w.ctl->error, 2u); gave_up = true; break; }
           uint64_t sw[LW];
 #pragma unroll
           for (uint32_t i = 0; i < LW; i++)
@@ -628,12 +632,13 @@ __global__ __launch_bounds__(WG) void k_tile_scan(Plan p, Work w, uint32_t level
           jc -= used;
           if (done) break;
           if (stall) {
-            if (++spins > LB_SPIN_LIMIT) { atomicOr(&w.ctl->error, 2u); break; }
+            ++spins;
             __builtin_amdgcn_s_sleep(1);
           }
         }
         // a chunk inside one bucket can now publish its inclusive sum too
-        if (!lin) atomic_store_agent(&cs[v], epoch | LB_INC | (run + agg));
+        // (not after a give-up: its carry is incomplete)
+        if (!lin && !gave_up) atomic_store_agent(&cs[v], epoch | LB_INC | (run + agg));
       }
       // 3. the tiles' offsets
       uint32_t b = b0, nxt = 0;
@@ -690,6 +695,8 @@ __global__ __launch_bounds__(WG) void k_scatter(Plan p, Work w, uint32_t level, 
   uint32_t nb = min((uint64_t)w.ctl->nbig[level], p.cap_big);
   uint64_t T = w.ctl->ntiles[level];
   if (nb == 0 || T == 0) return;
+  // a tile-offset scan that gave up leaves offsets that are not to be used
+  if (w.ctl->error & 2u) return;
   const KeyFmt kf = make_keyfmt(p.key_bytes);
   const uint32_t lane = lane_id();
   const uint32_t wave = threadIdx.x / 64;

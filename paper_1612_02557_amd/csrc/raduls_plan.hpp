@@ -41,7 +41,8 @@ struct Ctl {
   uint32_t class_count[NCLASS];
   uint64_t copy_tiles;
   uint32_t copy_ticket;
-  uint32_t error;              // bit 0: bad segment offsets, bit 1: look-back wait limit
+  uint32_t error;              // bit 0: bad segment offsets, bit 1: look-back wait limit (the
+                               // scatters that follow are skipped)
   uint32_t overflow;           // bit 0 big list, 1 small, 2 tiny, 3 copy, 4 stack, 5 deferred jobs
   uint32_t epoch;              // look-back epoch of level 0 of this sort
   uint32_t pad;
@@ -79,6 +80,8 @@ struct Plan {
   uint32_t has_model;
   uint32_t partition;      // 1: one level on one bucket, children not routed
   uint32_t partition_bit;  // resolved bits of that bucket
+  uint32_t spin_limit;     // polls a look-back wait makes before it gives up
+  uint32_t pad0;
   uint64_t trace_cap;
 };
 

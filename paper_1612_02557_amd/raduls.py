@@ -142,6 +142,25 @@ def _stream(stream):
     return stream.cuda_stream
 
 
+def _torch_stream(stream):
+    """The torch stream object for ``stream`` (None: the current stream)."""
+    import torch
+    if stream is None:
+        return torch.cuda.current_stream()
+    if isinstance(stream, int):
+        return torch.cuda.ExternalStream(stream)
+    return stream
+
+
+def _scratch_like(records, stream):
+    """tmp for one call, allocated on the stream the call runs on, so that
+    the caching allocator does not hand the block out again while the sort
+    still writes to it."""
+    import torch
+    with torch.cuda.stream(_torch_stream(stream)):
+        return torch.empty_like(records)
+
+
 def _records(t):
     import torch
     if t.dtype != torch.uint8 or t.dim() != 2 or not t.is_contiguous() or not t.is_cuda:
@@ -149,14 +168,19 @@ def _records(t):
     return t
 
 
-def sort(records, key_bytes: int, tmp=None, stream=None):
-    """Sort ``records`` (uint8 [n, rec_bytes] on the GPU) in place by key."""
-    import torch
+def sort(records, key_bytes: int, tmp=None, stream=None, check: bool = False):
+    """Sort ``records`` (uint8 [n, rec_bytes] on the GPU) in place by key.
+
+    With ``check`` the call waits for the stream and raises if a device-side
+    check failed (``raduls_sync_check``: look-back wait limit, queue
+    overflow)."""
     records = _records(records)
     n, r = records.shape
     if tmp is None:
-        tmp = torch.empty_like(records)
+        tmp = _scratch_like(records, stream)
     _check(lib().raduls_sort(records.data_ptr(), tmp.data_ptr(), n, r, key_bytes, _stream(stream)))
+    if check:
+        sync_check(stream)
     return records
 
 
@@ -165,21 +189,24 @@ def sort_ptr(records_ptr: int, tmp_ptr: int, n: int, rec_bytes: int, key_bytes: 
     return lib().raduls_sort(records_ptr, tmp_ptr, n, rec_bytes, key_bytes, stream)
 
 
-def sort_segmented(records, offsets, key_bytes: int, tmp=None, stream=None):
+def sort_segmented(records, offsets, key_bytes: int, tmp=None, stream=None, check: bool = False):
     """Sort each segment [offsets[s], offsets[s+1]) of ``records`` independently.
 
-    ``offsets`` is a CUDA int64/uint64 tensor of num_segs + 1 entries.
+    ``offsets`` is a CUDA int64/uint64 tensor of num_segs + 1 entries.  With
+    ``check`` the call waits and raises on a device-side failure (invalid
+    offsets included).
     """
-    import torch
     records = _records(records)
     n, r = records.shape
     if tmp is None:
-        tmp = torch.empty_like(records)
+        tmp = _scratch_like(records, stream)
     if not offsets.is_cuda or offsets.element_size() != 8 or not offsets.is_contiguous():
         raise ValueError("offsets must be a contiguous 8-byte CUDA tensor")
     S = offsets.numel() - 1
     _check(lib().raduls_sort_segmented(records.data_ptr(), tmp.data_ptr(), offsets.data_ptr(), S, n, r,
                                        key_bytes, _stream(stream)))
+    if check:
+        sync_check(stream)
     return records
 
 

@@ -128,3 +128,22 @@ def test_mlp_entry_validation(R):
 def test_tune_validation(R):
     assert R.lib().raduls_tune(6, 4, 1 << 20, None) == R.EUNSUPPORTED
     assert R.lib().raduls_tune(16, 0, 1 << 20, None) == R.EINVAL
+
+
+def test_digit_width_too_small_for_key_refused(R):
+    """A tuning whose digit width would need more multi-workgroup levels than
+    the plan holds (20) is refused before any device work: 16-byte keys at 6
+    bits need 23, 8-byte keys at 3 bits need 23."""
+    p = 1 << 20
+    t = R.default_tuning(32, 16, 1 << 20)
+    try:
+        t.big_digit_bits = 6
+        R.set_tuning(t)
+        assert R.sort_ptr(p, p + (1 << 30), 100, 32, 16, 0) == R.EUNSUPPORTED
+        assert "big_digit_bits" in R.lib().raduls_last_error_message().decode()
+        t.big_digit_bits = 3
+        R.set_tuning(t)
+        assert R.sort_ptr(p, p + (1 << 30), 100, 16, 8, 0) == R.EUNSUPPORTED
+        assert R.lib().raduls_sort_segmented(p, p + (1 << 30), p + (1 << 31), 3, 100, 16, 8, None) == R.EUNSUPPORTED
+    finally:
+        R.set_tuning(None)

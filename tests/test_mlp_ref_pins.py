@@ -71,6 +71,36 @@ def test_first_adam_step_closed_form(rng):
     np.testing.assert_allclose(v1, 0.001 * g * g)
 
 
+def test_adam_steps_two_and_three_by_hand():
+    """Adam at t = 2 and t = 3 against values worked out by hand (Kingma and
+    Ba, Algorithm 1) for beta1 = 1/2, beta2 = 3/4, lr = 1, eps = 0 and the
+    gradients 2, 1, -2 (one scalar parameter, replicated with three starting
+    values).  The bias corrections divide by 1 - beta**t, so t = 2 and t = 3
+    tell apart a correction by beta instead of beta**t (which would give a
+    step of exactly 1 at t = 2)."""
+    th0 = np.array([0.0, 1.5, -3.0])
+    z = np.zeros(3)
+    kw = dict(beta1=0.5, beta2=0.75, eps=0.0)
+    # t = 1: m1 = 1, v1 = 1, mhat = 2, vhat = 4, step 1
+    th1, m1, v1 = M.adam_step(th0, np.full(3, 2.0), z, z, 1, 1.0, **kw)
+    np.testing.assert_allclose(m1, 1.0)
+    np.testing.assert_allclose(v1, 1.0)
+    np.testing.assert_allclose(th1, th0 - 1.0)
+    # t = 2, g = 1: m2 = 1, v2 = 1, mhat = 1/(3/4) = 4/3,
+    # vhat = 1/(7/16) = 16/7, step = (4/3) / (4/sqrt 7) = sqrt(7)/3
+    th2, m2, v2 = M.adam_step(th1, np.full(3, 1.0), m1, v1, 2, 1.0, **kw)
+    np.testing.assert_allclose(m2, 1.0)
+    np.testing.assert_allclose(v2, 1.0)
+    np.testing.assert_allclose(th2, th1 - np.sqrt(7.0) / 3.0, rtol=1e-14)
+    # t = 3, g = -2: m3 = 1/2 - 1 = -1/2, v3 = 3/4 + 1 = 7/4,
+    # mhat = (-1/2)/(7/8) = -4/7, vhat = (7/4)/(37/64) = 112/37,
+    # step = (-4/7) / sqrt(112/37)
+    th3, m3, v3 = M.adam_step(th2, np.full(3, -2.0), m2, v2, 3, 1.0, **kw)
+    np.testing.assert_allclose(m3, -0.5)
+    np.testing.assert_allclose(v3, 1.75)
+    np.testing.assert_allclose(th3, th2 + (4.0 / 7.0) / np.sqrt(112.0 / 37.0), rtol=1e-14)
+
+
 def test_adam_reduces_loss(rng):
     X = rng.normal(size=(256, F))
     true_w = rng.normal(size=(P, F))
