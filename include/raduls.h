@@ -118,6 +118,24 @@ typedef struct raduls_stats {
 int raduls_sort(void* records, void* tmp, uint64_t n, uint32_t rec_bytes, uint32_t key_bytes,
                 void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * sort as raduls_sort, with the same arguments, results and argument
+ * checks, but its workspace is one fixed array of
+ * RADULS_NOALLOC_SCRATCH_BYTES per GPU inside the library (held until the
+ * process ends) and it calls no allocating routine.  A sort whose workspace
+ * (about raduls_workspace_bytes(n, ...)) does not fit that array returns
+ * RADULS_EUNSUPPORTED before any device work; 2^22 records of up to 32 bytes
+ * fit.  The caller still passes `records` and `tmp`.  All calls on one GPU
+ * share the array, so calls that overlap on one GPU (different streams, or
+ * threads) race and must be ordered by the caller.  The learned scheduler is
+ * used only if its network is already on the device (after a raduls_sort
+ * with it); otherwise the heuristic runs.  Tracing is off.  Device-side
+ * failures are reported by raduls_sync_check. */
+#define RADULS_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int raduls_sort_noalloc(void* records, void* tmp, uint64_t n, uint32_t rec_bytes, uint32_t key_bytes,
+                        void* stream);
+
 /* Sort each segment [seg_offsets[s], seg_offsets[s+1]) of `records`
  * independently (a batch of independent arrays), in one launch sequence that
  * the library captures once per shape into a HIP graph and replays.

@@ -268,6 +268,33 @@ void drop_graphs(DeviceState& s) {
   s.graphs.clear();
 }
 
+// Point a Work at a workspace laid out by `L`: `base` holds the lists,
+// histograms and queues (L.total bytes), `status` the epoch counter, tile
+// digit offsets and look-back words (L.status_total bytes).
+void bind_work(Work& w, const Layout& L, uint8_t* base, uint8_t* status) {
+  w.ctl = (rd::Ctl*)(base + L.ctl);
+  w.big = (rd::Bucket*)(base + L.big);
+  w.tile_start = (uint64_t*)(base + L.tile_start);
+  w.hist = (uint64_t*)(base + L.hist);
+  w.vary = (uint64_t*)(base + L.vary);
+  w.status = (uint64_t*)(status + 256);
+  w.cstatus = (uint64_t*)(status + L.cstatus);
+  w.tcnt = (uint32_t*)(base + L.tcnt);
+  w.tbucket = (uint32_t*)(base + L.tbucket);
+  w.small = (rd::Bucket*)(base + L.small);
+  w.small_ord = (rd::Bucket*)(base + L.small_ord);
+  w.tiny = (uint64_t*)(base + L.tiny);
+  w.copy = (rd::Bucket*)(base + L.copy);
+  w.copy_start = (uint64_t*)(base + L.copy_start);
+  w.stacks = (rd::Bucket*)(base + L.stacks);
+  w.wgjobs = (rd::Bucket*)(base + L.wgjobs);
+  w.model = nullptr;
+  w.trace = nullptr;
+  w.trace_count = (uint64_t*)(base + L.trace_count);
+  w.counts_out = nullptr;
+  w.epoch_counter = (uint32_t*)status;
+}
+
 // Make sure the workspace holds the plan's layout.  The look-back words live
 // in an allocation of their own, zeroed when it is (re)allocated and when the
 // epochs run out, so a stale word can only be an old status word.
@@ -314,28 +341,9 @@ int ensure_workspace(DeviceState& s, const Plan& p, Layout& L, hipStream_t strea
     HIPCHK(hipMemsetAsync(s.status_base, 0, s.status_bytes, stream));
     s.epochs_used = 0;
   }
-  Work& w = s.work;
-  w.ctl = (rd::Ctl*)(s.base + L.ctl);
-  w.big = (rd::Bucket*)(s.base + L.big);
-  w.tile_start = (uint64_t*)(s.base + L.tile_start);
-  w.hist = (uint64_t*)(s.base + L.hist);
-  w.vary = (uint64_t*)(s.base + L.vary);
-  w.status = (uint64_t*)(s.status_base + 256);
-  w.cstatus = (uint64_t*)(s.status_base + L.cstatus);
-  w.tcnt = (uint32_t*)(s.base + L.tcnt);
-  w.tbucket = (uint32_t*)(s.base + L.tbucket);
-  w.small = (rd::Bucket*)(s.base + L.small);
-  w.small_ord = (rd::Bucket*)(s.base + L.small_ord);
-  w.tiny = (uint64_t*)(s.base + L.tiny);
-  w.copy = (rd::Bucket*)(s.base + L.copy);
-  w.copy_start = (uint64_t*)(s.base + L.copy_start);
-  w.stacks = (rd::Bucket*)(s.base + L.stacks);
-  w.wgjobs = (rd::Bucket*)(s.base + L.wgjobs);
-  w.model = g_model_loaded ? s.model : nullptr;
-  w.trace = s.trace;
-  w.trace_count = (uint64_t*)(s.base + L.trace_count);
-  w.counts_out = nullptr;
-  w.epoch_counter = (uint32_t*)s.status_base;
+  bind_work(s.work, L, s.base, s.status_base);
+  s.work.model = g_model_loaded ? s.model : nullptr;
+  s.work.trace = s.trace;
   return RADULS_OK;
 }
 
@@ -393,34 +401,39 @@ struct PhaseMarks {
 // The launch sequence of one sort.  Every kernel reads its work from
 // device-side lists, so the sequence is the same for any data and can be
 // captured into a graph.
+void enqueue_launches(const Plan& p, const Work& w, void* records, void* tmp, const uint64_t* off, uint32_t S,
+                      hipStream_t st, PhaseMarks& pm) {
+  pm.mark(-1);
+  rd::launch_init(w, st);
+  if (off) rd::launch_seed_segments(p, w, off, S, st);
+  else rd::launch_seed_single(p, w, st);
+  pm.mark(0);
+  for (uint32_t l = 0; l < p.lmax; l++) {
+    rd::launch_level_prep(p, w, l, st);
+    pm.mark(1 + 4 * l);
+    rd::launch_level_hist(p, w, l, records, tmp, st);
+    pm.mark(2 + 4 * l);
+    rd::launch_level_scan(p, w, l, st);
+    rd::launch_tile_scan(p, w, l, st);
+    pm.mark(3 + 4 * l);
+    rd::launch_level_scatter(p, w, l, records, tmp, st);
+    pm.mark(4 + 4 * l);
+  }
+  rd::launch_order_small(p, w, st);
+  pm.mark(PH_ORDER);
+  rd::launch_small(p, w, records, tmp, st);
+  pm.mark(PH_SMALL);
+  rd::launch_small_jobs(p, w, records, tmp, st);
+  pm.mark(PH_JOBS);
+  rd::launch_copy(p, w, records, tmp, st);
+  pm.mark(PH_COPY);
+}
+
 void enqueue_sort(DeviceState& s, const Plan& p, void* records, void* tmp, const uint64_t* off, uint32_t S,
                   hipStream_t st, bool phases) {
   PhaseMarks pm{&s, st, phases};
   s.ph_id.clear();
-  pm.mark(-1);
-  rd::launch_init(s.work, st);
-  if (off) rd::launch_seed_segments(p, s.work, off, S, st);
-  else rd::launch_seed_single(p, s.work, st);
-  pm.mark(0);
-  for (uint32_t l = 0; l < p.lmax; l++) {
-    rd::launch_level_prep(p, s.work, l, st);
-    pm.mark(1 + 4 * l);
-    rd::launch_level_hist(p, s.work, l, records, tmp, st);
-    pm.mark(2 + 4 * l);
-    rd::launch_level_scan(p, s.work, l, st);
-    rd::launch_tile_scan(p, s.work, l, st);
-    pm.mark(3 + 4 * l);
-    rd::launch_level_scatter(p, s.work, l, records, tmp, st);
-    pm.mark(4 + 4 * l);
-  }
-  rd::launch_order_small(p, s.work, st);
-  pm.mark(PH_ORDER);
-  rd::launch_small(p, s.work, records, tmp, st);
-  pm.mark(PH_SMALL);
-  rd::launch_small_jobs(p, s.work, records, tmp, st);
-  pm.mark(PH_JOBS);
-  rd::launch_copy(p, s.work, records, tmp, st);
-  pm.mark(PH_COPY);
+  enqueue_launches(p, s.work, records, tmp, off, S, st, pm);
   s.ph_valid = phases;
 }
 
@@ -435,6 +448,51 @@ int prepare(DeviceState& s, Plan& p, Layout& L, hipStream_t st) {
   s.work.model = g_model_loaded ? s.model : nullptr;
   s.work.trace = s.trace;
   return RADULS_OK;
+}
+
+// ---- sorting without allocation ----------------------------------------------
+// One fixed device array serves every call of raduls_sort_noalloc on a GPU:
+// its workspace (control block, lists, counts, queues) and its look-back
+// words.  In host code `scratch` only names the symbol; its device address
+// on each GPU comes from hipGetSymbolAddress and is kept in g_noalloc.
+constexpr size_t NOALLOC_BYTES = (size_t)RADULS_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) uint8_t scratch[NOALLOC_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+struct NoAllocDev {
+  uint8_t* ptr = nullptr;      // device address of `scratch` on this GPU
+  bool cleared = false;        // zeroed once by a fill kernel
+  uint64_t epochs_used = 0;    // look-back epochs handed out since the last clear
+  rd::Ctl* ctl = nullptr;      // control block of the last call (for raduls_sync_check)
+};
+NoAllocDev g_noalloc[NOALLOC_MAX_DEVICES];
+
+// Set-up, once per device with that device current.
+int noalloc_device(int dev, NoAllocDev*& out) {
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(RADULS_EUNSUPPORTED, "device index above 63");
+  NoAllocDev& d = g_noalloc[dev];
+  if (!d.ptr) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!ptr) return fail(RADULS_EHIP, "hipGetSymbolAddress(scratch) returned null");
+    d.ptr = (uint8_t*)ptr;
+  }
+  out = &d;
+  return RADULS_OK;
+}
+
+// Device-side flags of one control block; clears them.
+int check_ctl(rd::Ctl* ctl) {
+  rd::Ctl c;
+  HIPCHK(hipMemcpy(&c, ctl, sizeof(c), hipMemcpyDeviceToHost));
+  if (c.error == 0 && c.overflow == 0) return RADULS_OK;
+  const uint32_t zero[2] = {0, 0};
+  static_assert(offsetof(rd::Ctl, overflow) == offsetof(rd::Ctl, error) + 4, "error and overflow are adjacent");
+  HIPCHK(hipMemcpy(&ctl->error, zero, sizeof(zero), hipMemcpyHostToDevice));
+  if (c.error & 1u) return fail(RADULS_EDEVICE, "segment offsets invalid (must start at 0, not decrease, end at total)");
+  if (c.error & 2u) return fail(RADULS_EDEVICE, "look-back wait limit reached");
+  return fail(RADULS_EDEVICE, "a device queue overflowed");
 }
 
 }  // namespace
@@ -477,6 +535,61 @@ int raduls_sort(void* records, void* tmp, uint64_t n, uint32_t rec_bytes, uint32
   g_stats.last_records = n;
   g_stats.last_levels = p.lmax;
   return mark_done(s, st);
+}
+
+int raduls_sort_noalloc(void* records, void* tmp, uint64_t n, uint32_t rec_bytes, uint32_t key_bytes, void* stream) {
+  int rc = check_shape(rec_bytes, key_bytes);
+  if (rc) return rc;
+  if (n <= 1) return RADULS_OK;
+  if (!records || !tmp) return fail(RADULS_EINVAL, "null records or tmp");
+  if (n >= (1ull << 40)) return fail(RADULS_EUNSUPPORTED, "n must be below 2^40");
+  if (((uintptr_t)records & 15) || ((uintptr_t)tmp & 15)) return fail(RADULS_EINVAL, "buffers must be 16-byte aligned");
+  if (overlap(records, tmp, n * rec_bytes)) return fail(RADULS_EINVAL, "records and tmp overlap");
+  std::lock_guard<std::mutex> lock(g_mu);
+  raduls_tuning t = current_tuning(rec_bytes, key_bytes, n);
+  rc = check_levels(key_bytes, t);
+  if (rc) return rc;
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) {
+    (void)hipGetLastError();
+    cus = 256;
+  }
+  Plan p = make_plan(n, rec_bytes, key_bytes, t, cus, 0);
+  const Layout L = layout_of(p);
+  const size_t base_off = align_up(L.status_total);
+  if (base_off + L.total > NOALLOC_BYTES)
+    return fail(RADULS_EUNSUPPORTED, "sort needs more workspace than the no-allocation scratch holds");
+  NoAllocDev* d = nullptr;
+  rc = noalloc_device(dev, d);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  // zeroed before the first use on this device and when the look-back
+  // epochs run out, by a fill kernel on the caller's stream
+  if (!d->cleared || d->epochs_used + rd::LMAX + 1 >= EPOCH_LIMIT) {
+    rd::launch_zero(d->ptr, NOALLOC_BYTES, st);
+    d->cleared = true;
+    d->epochs_used = 0;
+  }
+  Work w{};
+  bind_work(w, L, d->ptr + base_off, d->ptr);
+  // the learned scheduler runs only if its network is resident on this
+  // device already (uploading it would allocate); otherwise the heuristic
+  auto it = g_dev.find(dev);
+  const bool resident = g_model_loaded && it != g_dev.end() && it->second.model &&
+                        it->second.model_version == g_model_version;
+  if (p.sched_mode == RADULS_SCHED_LEARNED && !resident) p.sched_mode = RADULS_SCHED_HEURISTIC;
+  p.has_model = resident ? 1 : 0;
+  w.model = resident ? it->second.model : nullptr;
+  p.trace_cap = 0;
+  p.sample_period = 0;
+  PhaseMarks pm{nullptr, st, false};
+  enqueue_launches(p, w, records, tmp, nullptr, 0, st, pm);
+  HIPCHK(hipGetLastError());
+  d->epochs_used += rd::LMAX + 1;
+  d->ctl = w.ctl;
+  return RADULS_OK;
 }
 
 int raduls_sort_segmented(void* records, void* tmp, const uint64_t* seg_offsets, uint32_t num_segs,
@@ -629,18 +742,14 @@ int raduls_sync_check(void* stream) {
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
   HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+  int rc = RADULS_OK;
   auto it = g_dev.find(dev);
-  if (it == g_dev.end() || !it->second.base) return RADULS_OK;
-  rd::Ctl c;
-  HIPCHK(hipMemcpy(&c, it->second.work.ctl, sizeof(c), hipMemcpyDeviceToHost));
-  if (c.error == 0 && c.overflow == 0) return RADULS_OK;
-  // report once: clear the flags (the stream is idle, the copy is ordered)
-  const uint32_t zero[2] = {0, 0};
-  static_assert(offsetof(rd::Ctl, overflow) == offsetof(rd::Ctl, error) + 4, "error and overflow are adjacent");
-  HIPCHK(hipMemcpy(&it->second.work.ctl->error, zero, sizeof(zero), hipMemcpyHostToDevice));
-  if (c.error & 1u) return fail(RADULS_EDEVICE, "segment offsets invalid (must start at 0, not decrease, end at total)");
-  if (c.error & 2u) return fail(RADULS_EDEVICE, "look-back wait limit reached");
-  return fail(RADULS_EDEVICE, "a device queue overflowed");
+  if (it != g_dev.end() && it->second.base) rc = check_ctl(it->second.work.ctl);
+  if (dev >= 0 && dev < NOALLOC_MAX_DEVICES && g_noalloc[dev].ctl) {
+    int rc2 = check_ctl(g_noalloc[dev].ctl);
+    if (rc == RADULS_OK) rc = rc2;
+  }
+  return rc;
 }
 
 int raduls_set_scheduler(int mode, int forced_proc) {

@@ -150,6 +150,13 @@ __global__ void k_clear_hist(Plan p, Work w, uint32_t level) {
     w.vary[i] = 0;
 }
 
+// Zero `words` 64-bit words (a fill kernel, so that the clearing can sit in
+// a captured stream without a memset node).
+__global__ void k_zero_words(uint64_t* p, uint64_t words) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < words; i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
 template <int RW, int DB>
 __global__ __launch_bounds__(WG) void k_hist(Plan p, Work w, uint32_t level, const uint8_t* rec0,
                                              const uint8_t* rec1) {
@@ -916,6 +923,14 @@ void launch_level_prep(const Plan& p, const Work& w, uint32_t level, hipStream_t
                             w.tile_start + (uint64_t)level * (p.cap_big + 1), &w.ctl->ntiles[level],
                             &w.ctl->ticket[level], p.tile);
   k_clear_hist<<<p.grid_clear, WG, 0, s>>>(p, w, level);
+}
+
+void launch_zero(void* p, size_t bytes, hipStream_t s) {
+  const uint64_t words = bytes / 8;
+  if (!words) return;
+  const uint64_t blocks = (words + WG - 1) / WG;
+  const uint32_t g = (uint32_t)(blocks < 4096 ? blocks : 4096);
+  k_zero_words<<<g, WG, 0, s>>>((uint64_t*)p, words);
 }
 
 void launch_level_hist(const Plan& p, const Work& w, uint32_t level, void* records, void* tmp, hipStream_t s) {

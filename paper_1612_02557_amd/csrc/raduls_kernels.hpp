@@ -7,6 +7,8 @@
 namespace rd {
 
 void launch_init(const Work& w, hipStream_t s);
+// zero `bytes` (a multiple of 8) at device address p with a fill kernel
+void launch_zero(void* p, size_t bytes, hipStream_t s);
 void launch_probe_fill(void* rec, uint64_t n, uint32_t rec_bytes, uint32_t key_bytes, uint64_t salt, uint64_t distinct,
                        hipStream_t s);
 void launch_seed_single(const Plan& p, const Work& w, hipStream_t s);

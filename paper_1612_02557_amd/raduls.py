@@ -72,6 +72,7 @@ TRACE_ROW_BYTES = ctypes.sizeof(TraceRow)
 
 _SIGS = {
     "raduls_sort": (_i32, [_vp, _vp, _u64, _u32, _u32, _vp]),
+    "raduls_sort_noalloc": (_i32, [_vp, _vp, _u64, _u32, _u32, _vp]),
     "raduls_tune": (_i32, [_u32, _u32, _u64, _vp]),
     "raduls_sort_segmented": (_i32, [_vp, _vp, _vp, _u32, _u64, _u32, _u32, _vp]),
     "raduls_partition": (_i32, [_vp, _vp, _u64, _u32, _u32, _u32, _u32, _vp, _vp]),
@@ -179,6 +180,24 @@ def sort(records, key_bytes: int, tmp=None, stream=None, check: bool = False):
     if tmp is None:
         tmp = _scratch_like(records, stream)
     _check(lib().raduls_sort(records.data_ptr(), tmp.data_ptr(), n, r, key_bytes, _stream(stream)))
+    if check:
+        sync_check(stream)
+    return records
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def sort_noalloc(records, key_bytes: int, tmp, stream=None, check: bool = False):
+    """``sort`` through ``raduls_sort_noalloc``: the library allocates no
+    device memory (its workspace is a fixed array of NOALLOC_SCRATCH_BYTES
+    per GPU), so ``tmp`` must be given."""
+    records = _records(records)
+    tmp = _records(tmp)
+    n, r = records.shape
+    if tmp.shape[0] < n or tmp.shape[1] != r:
+        raise ValueError("tmp must hold at least as many records of the same size")
+    _check(lib().raduls_sort_noalloc(records.data_ptr(), tmp.data_ptr(), n, r, key_bytes, _stream(stream)))
     if check:
         sync_check(stream)
     return records

@@ -147,3 +147,14 @@ def test_digit_width_too_small_for_key_refused(R):
         assert R.lib().raduls_sort_segmented(p, p + (1 << 30), p + (1 << 31), 3, 100, 16, 8, None) == R.EUNSUPPORTED
     finally:
         R.set_tuning(None)
+
+
+def test_noalloc_validation(R):
+    f = R.lib().raduls_sort_noalloc
+    p = 1 << 20
+    assert f(p, p + (1 << 30), 100, 6, 4, 0) == R.EUNSUPPORTED     # rec_bytes % 4
+    assert f(p, p + (1 << 30), 100, 16, 0, 0) == R.EINVAL          # key_bytes == 0
+    assert f(0, 0, 100, 16, 8, 0) == R.EINVAL                      # null buffers
+    assert f(p, p + 800, 100, 16, 8, 0) == R.EINVAL                # records and tmp overlap
+    assert f(p + 4, p + (1 << 30), 100, 16, 8, 0) == R.EINVAL      # misaligned
+    assert f(0, 0, 1, 16, 8, 0) == R.OK                            # n <= 1: nothing to do
