@@ -85,7 +85,9 @@ typedef struct raduls_tuning {
                                  1: big_min alone (the default, with big_min = 2 tiles) */
   uint32_t job_records;       /* children of a radix pass are grouped into finishing jobs of at
                                  most this many records (0 = the LDS capacity) */
-  uint32_t reserved;
+  uint32_t reg_finish;        /* 1: keys of at most 8 bytes are finished by 1024-thread workgroups
+                                 holding up to 17K records in registers (buckets that size leave
+                                 the levels); 0: by the LDS procedures of at most the LDS capacity */
 } raduls_tuning;
 
 /* One row per scheduled bucket when tracing is on (64 bytes). */

@@ -134,6 +134,7 @@ raduls_tuning default_tuning(uint32_t r, uint32_t k, uint64_t n) {
   t.big_min = 2ull * t.tile_records;
   t.big_rule = 1;
   t.nontemporal = 0;
+  t.reg_finish = 1;
   return t;
 }
 
@@ -145,11 +146,31 @@ int validate_tuning(const raduls_tuning& t) {
   if (t.workgroups_per_cu < 1 || t.workgroups_per_cu > 8) return fail(RADULS_EINVAL, "workgroups_per_cu must be 1..8");
   if (t.big_rule > 1) return fail(RADULS_EINVAL, "big_rule must be 0 or 1");
   if (t.job_records != 0 && t.job_records < 64) return fail(RADULS_EINVAL, "job_records must be 0 or >= 64");
+  if (t.reg_finish > 1) return fail(RADULS_EINVAL, "reg_finish must be 0 or 1");
   return RADULS_OK;
 }
 
+// LDS a workgroup may hold on the current device (0 if unknown).
+int device_lds_per_block() {
+  static std::map<int, int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) { (void)hipGetLastError(); return 0; }
+  auto it = cache.find(dev);
+  if (it != cache.end()) return it->second;
+  int v = 0;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    v = 0;
+  }
+  cache[dev] = v;
+  return v;
+}
+
 // Launch plan for n records (paper, Sec. 3.2: big bins above 2N/(3T)).
-Plan make_plan(uint64_t n, uint32_t r, uint32_t k, const raduls_tuning& t, int cus, uint32_t segs) {
+// `allow_fin`: finishing jobs may run in registers (not while tracing,
+// whose rows come from the LDS procedures).
+Plan make_plan(uint64_t n, uint32_t r, uint32_t k, const raduls_tuning& t, int cus, uint32_t segs,
+               bool allow_fin = true) {
   Plan p{};
   p.n = n;
   p.rec_bytes = r;
@@ -186,10 +207,35 @@ Plan make_plan(uint64_t n, uint32_t r, uint32_t k, const raduls_tuning& t, int c
   p.grid_clear = cus * 4;
   uint64_t W = p.grid_small;
   p.t_big = std::max<uint64_t>(t.big_min, (uint64_t)p.c_fin);
+  // Register finishing (keys of at most 8 bytes, heuristic scheduling): a
+  // 1024-thread workgroup finishes jobs of up to fin_max records, so
+  // buckets up to that size leave the levels.
+  p.fin_max = 0;
+  p.grid_fin = cus;
+  const int lds_limit = device_lds_per_block();
+  if (allow_fin && t.reg_finish && k <= 8 && g_sched_mode == RADULS_SCHED_HEURISTIC &&
+      (lds_limit <= 0 || lds_limit >= (int)(rd::FIN_LDS_BYTES + 4096))) {
+    p.fin_max = rd::fin_records_per_thread(p.rw) * rd::FIN_THREADS;
+    p.t_big = std::max<uint64_t>(t.big_min, (uint64_t)p.fin_max);
+    const uint32_t fjob = t.job_records ? std::min<uint32_t>(std::max<uint32_t>(t.job_records, p.c_fin), p.fin_max)
+                                        : p.fin_max;
+    p.job_window = std::max<uint32_t>(32, fjob / 2);
+  }
   if (t.big_rule == 0) p.t_big = std::max<uint64_t>(p.t_big, 2 * n / (3 * W));
   uint32_t kb = 8 * k;
   p.lmax = std::min<uint32_t>((kb + p.d_big - 1) / p.d_big + 1, rd::LMAX);
   p.cap_big = n / (p.t_big + 1) + 2;
+  if (p.fin_max) {
+    // With register finishing a bucket also takes a level when its
+    // composite would not fit 64 bits, which depends on its resolved bits:
+    // a bucket below a level has at least d_big of them (the root and the
+    // segments have none).
+    const uint32_t kb = 8 * k, b1 = std::min<uint32_t>(p.d_big, kb);
+    const uint32_t below = kb - b1 > rd::FIN_DIGIT_BITS ? kb - b1 - rd::FIN_DIGIT_BITS : 0;
+    const uint32_t ibmax = 64 - below;
+    const uint64_t cap1 = ibmax >= 32 ? p.fin_max : std::min<uint64_t>(p.fin_max, 1ull << ibmax);
+    p.cap_big = n / (std::min<uint64_t>(p.t_big, cap1) + 1) + 2 + std::min<uint64_t>(segs, n / 33 + 1);
+  }
   uint64_t R = 1ull << p.d_big;
   uint64_t child_bound = R * p.lmax * p.cap_big + segs + 1;
   p.cap_small = std::min<uint64_t>(n / 33 + 1, child_bound) + 1;
@@ -423,7 +469,8 @@ void enqueue_launches(const Plan& p, const Work& w, void* records, void* tmp, co
   pm.mark(PH_ORDER);
   rd::launch_small(p, w, records, tmp, st);
   pm.mark(PH_SMALL);
-  rd::launch_small_jobs(p, w, records, tmp, st);
+  if (p.fin_max) rd::launch_fin_jobs(p, w, records, tmp, st);
+  else rd::launch_small_jobs(p, w, records, tmp, st);
   pm.mark(PH_JOBS);
   rd::launch_copy(p, w, records, tmp, st);
   pm.mark(PH_COPY);
@@ -515,7 +562,7 @@ int raduls_sort(void* records, void* tmp, uint64_t n, uint32_t rec_bytes, uint32
   HIPCHK(hipGetDevice(&dev));
   DeviceState& s = state_for(dev);
   hipStream_t st = (hipStream_t)stream;
-  Plan p = make_plan(n, rec_bytes, key_bytes, t, s.cu_count, 0);
+  Plan p = make_plan(n, rec_bytes, key_bytes, t, s.cu_count, 0, s.trace == nullptr);
   Layout L;
   // ordered after the previous call before anything (a workspace reset
   // included) touches the workspace on this stream
@@ -610,7 +657,7 @@ int raduls_sort_segmented(void* records, void* tmp, const uint64_t* seg_offsets,
   HIPCHK(hipGetDevice(&dev));
   DeviceState& s = state_for(dev);
   hipStream_t st = (hipStream_t)stream;
-  Plan p = make_plan(total_records, rec_bytes, key_bytes, t, s.cu_count, num_segs);
+  Plan p = make_plan(total_records, rec_bytes, key_bytes, t, s.cu_count, num_segs, s.trace == nullptr);
   Layout L;
   rc = order_after_previous(s, st);
   if (rc) return rc;
@@ -665,7 +712,7 @@ int raduls_partition(const void* in, void* out, uint64_t n, uint32_t rec_bytes, 
   hipStream_t st = (hipStream_t)stream;
   raduls_tuning t = current_tuning(rec_bytes, key_bytes, n);
   t.big_digit_bits = bits;
-  Plan p = make_plan(n, rec_bytes, key_bytes, t, s.cu_count, 0);
+  Plan p = make_plan(n, rec_bytes, key_bytes, t, s.cu_count, 0, false);
   p.lmax = 1;
   p.partition = 1;
   p.t_big = 0;

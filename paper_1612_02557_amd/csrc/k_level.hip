@@ -56,6 +56,11 @@ __device__ __forceinline__ void push_tiny(const Plan& p, const Work& w, uint64_t
   if (i < p.cap_tiny) w.tiny[i] = packed;
   else atomicOr(&w.ctl->overflow, 4u);
 }
+__device__ __forceinline__ void push_job(const Plan& p, const Work& w, const Bucket& b) {
+  uint32_t i = atomicAdd(&w.ctl->nwg, 1u);
+  if (i < p.cap_wg) w.wgjobs[i] = b;
+  else atomicOr(&w.ctl->overflow, 32u);
+}
 __device__ __forceinline__ void push_copy(const Plan& p, const Work& w, const Bucket& b) {
   uint32_t i = atomicAdd(&w.ctl->ncopy, 1u);
   if (i < p.cap_copy) w.copy[i] = b;
@@ -71,6 +76,21 @@ __device__ void route_bucket(const Plan& p, const Work& w, uint32_t next_level, 
     if (!in_tmp || b.count == 0) return;
     if (b.count <= 63) push_tiny(p, w, pack_tiny(b.begin, (uint32_t)b.count, 1u, kbits));
     else push_copy(p, w, b);
+    return;
+  }
+  if (p.fin_max) {
+    // register finishing: every bucket that qualifies as a job is one;
+    // the others take another level while levels are left
+    if (b.count <= TINY_MAX) {
+      push_tiny(p, w, pack_tiny(b.begin, (uint32_t)b.count, in_tmp ? 1u : 0u, b.bit));
+    } else if (job_ok(p, b.count, b.bit, kbits)) {
+      b.flags |= BF_ROOT;
+      push_job(p, w, b);
+    } else if (next_level < p.lmax) {
+      push_big(p, w, next_level, b);
+    } else {
+      push_small(p, w, b);
+    }
     return;
   }
   if (b.count > p.t_big && next_level < p.lmax) {
@@ -459,7 +479,9 @@ __global__ __launch_bounds__(WG) void k_scan(Plan p, Work w, uint32_t level) {
       // by the window of V = J - (largest of them) records their first
       // record falls in, so a group holds under V + largest <= J records.
       const uint32_t t = threadIdx.x;
-      const uint64_t T = p.job_window;
+      // a group keeps the parent's resolved bits: its size is bounded by
+      // what a job with those bits may hold
+      const uint64_t T = min((uint64_t)p.job_window, max<uint64_t>(job_cap(p, B.bit, kf.kbits) / 2, 32));
       const uint64_t cnt = t < R ? off[t] : 0ull;
       if (t < R) gh[t] = run;  // digit base, read by the scatter
       flag[t] = cnt > 0 ? 1u : 0u;
@@ -500,7 +522,7 @@ __global__ __launch_bounds__(WG) void k_scan(Plan p, Work w, uint32_t level) {
         ch.parent = B.count;
         ch.bit = m == gfc[t] ? B.bit + d : B.bit;
         ch.flags = (B.flags & BF_TMP) ^ BF_TMP;
-        direct = m > TINY_MAX && m <= p.c_fin && ch.bit < kf.kbits;
+        direct = job_ok(p, m, ch.bit, kf.kbits);
         if (!direct) route_bucket(p, w, level + 1, ch, kf.kbits);
       }
       flag[t] = direct ? 1u : 0u;

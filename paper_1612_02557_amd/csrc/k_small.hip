@@ -1098,8 +1098,11 @@ __device__ __forceinline__ void build_jobs(Ctx& c) {
   SmallShared& S = *c.S;
   const uint32_t C = c.p.c_fin;
   const uint32_t WSC = c.p.wave_cap;
-  const uint32_t T = c.p.job_window;
   const uint32_t KB = c.kf.kbits;
+  // with register finishing, groups keep the parent's resolved bits and are
+  // bounded by what a job with those bits may hold
+  const uint32_t T = c.p.fin_max ? (uint32_t)min<uint64_t>(c.p.job_window, max<uint64_t>(job_cap(c.p, S.pbit, KB) / 2, 32))
+                                 : c.p.job_window;
   const uint32_t R = S.cR;
   const uint32_t t = threadIdx.x;
   // 1. compact the non-empty children (stable)
@@ -1140,6 +1143,12 @@ __device__ __forceinline__ void build_jobs(Ctx& c) {
     const uint32_t m = S.cbase[j + 1] - js;
     const uint32_t bit = m == S.ccnt[j] ? cb : pb;
     const uint32_t ib = 32 - __clz(m > 1 ? m - 1 : 1);
+    if (m > C && c.p.fin_max && job_ok(c.p, m, bit, KB)) {
+      uint32_t i = atomicAdd(&c.w.ctl->nwg, 1u);
+      if (i < c.p.cap_wg) c.w.wgjobs[i] = Bucket{S.cbegin + js, m, parent, bit, ctmp ? BF_TMP : 0u};
+      else atomicOr(&c.w.ctl->overflow, 32u);
+      continue;
+    }
     if (m > C) {
       uint32_t sp = atomicAdd(&S.sp, 1u);
       if (sp < c.p.stack_cap) c.stack[sp] = Bucket{S.cbegin + js, m, parent, cb, ctmp ? BF_TMP : 0u};

@@ -320,6 +320,37 @@ __device__ __forceinline__ uint64_t pack_tiny(uint64_t begin, uint32_t count, ui
   return begin | ((uint64_t)count << 40) | ((uint64_t)tmp << 46) | ((uint64_t)bit << 47);
 }
 
+// ---- finishing jobs ---------------------------------------------------------
+
+// Index bits of a job of m >= 2 records.
+__device__ __forceinline__ uint32_t index_bits(uint64_t m) { return 64u - (uint32_t)__clzll(m - 1); }
+
+// Key bits a finishing job of the register kernel keeps below its digit when
+// `bit` leading bits are resolved (its keys share them): what is left after
+// the FIN_DIGIT_BITS digit.  With the index bits they must fit 64 bits.
+__device__ __forceinline__ bool fin_fits(uint64_t m, uint32_t bit, uint32_t kbits) {
+  const uint32_t rem = kbits - bit;
+  const uint32_t below = rem > FIN_DIGIT_BITS ? rem - FIN_DIGIT_BITS : 0u;
+  return below + index_bits(m) <= 64;
+}
+
+// Can a bucket (or a group of consecutive children) of m records with `bit`
+// resolved bits be a finishing job of the plan's job kernel?
+__device__ __forceinline__ bool job_ok(const Plan& p, uint64_t m, uint32_t bit, uint32_t kbits) {
+  if (m <= TINY_MAX || bit >= kbits) return false;
+  if (!p.fin_max) return m <= p.c_fin;
+  return m <= p.fin_max && fin_fits(m, bit, kbits);
+}
+
+// Largest finishing job whose keys share `bit` leading bits.
+__device__ __forceinline__ uint64_t job_cap(const Plan& p, uint32_t bit, uint32_t kbits) {
+  if (!p.fin_max) return p.c_fin;
+  const uint32_t rem = kbits - bit;
+  const uint32_t below = rem > FIN_DIGIT_BITS ? rem - FIN_DIGIT_BITS : 0u;
+  const uint32_t ibmax = 64 - below;  // at least 11
+  return ibmax >= 32 ? (uint64_t)p.fin_max : min((uint64_t)p.fin_max, 1ull << ibmax);
+}
+
 // ---- look-back status words ----------------------------------------------
 // epoch (22 bits) << 42 | flag (2) << 40 | value (40): flag 1 = the tile's own
 // count (aggregate), flag 2 = the count of this and all earlier tiles of the

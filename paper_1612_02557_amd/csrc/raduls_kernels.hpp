@@ -21,6 +21,7 @@ void launch_level_scatter(const Plan& p, const Work& w, uint32_t level, void* re
 void launch_order_small(const Plan& p, const Work& w, hipStream_t s);
 void launch_small(const Plan& p, const Work& w, void* records, void* tmp, hipStream_t s);
 void launch_small_jobs(const Plan& p, const Work& w, void* records, void* tmp, hipStream_t s);
+void launch_fin_jobs(const Plan& p, const Work& w, void* records, void* tmp, hipStream_t s);
 void launch_copy(const Plan& p, const Work& w, void* records, const void* tmp, hipStream_t s);
 
 // scheduler network

@@ -24,6 +24,17 @@ constexpr uint32_t TINY_MAX = 32;    // buckets this small go to one wavefront (
 constexpr uint32_t SMALL_LDS_BYTES = 80 * 1024;  // dynamic LDS of the single-workgroup kernel
 constexpr uint32_t NCLASS = 40;      // size classes of the queued buckets (floor(log2(count)))
 
+// Finishing jobs held in registers (k_finish.hip): a 1024-thread workgroup
+// holds fin_records_per_thread(rw) records per thread (at most 68 words),
+// sorts composites of (key bits below an 11-bit digit, index) in LDS.
+constexpr uint32_t FIN_THREADS = 1024;
+constexpr uint32_t FIN_DIGIT_BITS = 11;
+__host__ __device__ constexpr uint32_t fin_records_per_thread(uint32_t rw) { return 68 / rw < 17 ? 68 / rw : 17; }
+constexpr uint32_t FIN_MAX_RECORDS = 17 * FIN_THREADS;
+constexpr uint32_t FIN_LDS_BYTES = 147712;  // composites of the largest job and 2^11 + 1 counters
+constexpr uint32_t FIN_LDS_BIG = 544;       // > FIN_MAX_RECORDS / 33: sub-bins above 32 records
+static_assert(FIN_LDS_BYTES >= 8 * FIN_MAX_RECORDS + 4 * ((1u << FIN_DIGIT_BITS) + 1), "LDS of a finishing job");
+
 // Device control block: list sizes, tickets, flags.  Cleared at the start of
 // every sort by the init kernel.
 struct Ctl {
@@ -42,7 +53,8 @@ struct Ctl {
   uint64_t copy_tiles;
   uint32_t copy_ticket;
   uint32_t error;              // bit 0: bad segment offsets, bit 1: look-back wait limit (the
-                               // scatters that follow are skipped)
+                               // scatters that follow are skipped), bit 2: a finishing job the
+                               // register kernel cannot take (never queued by the routing)
   uint32_t overflow;           // bit 0 big list, 1 small, 2 tiny, 3 copy, 4 stack, 5 deferred jobs
   uint32_t epoch;              // look-back epoch of level 0 of this sort
   uint32_t pad;
@@ -81,6 +93,8 @@ struct Plan {
   uint32_t partition;      // 1: one level on one bucket, children not routed
   uint32_t partition_bit;  // resolved bits of that bucket
   uint32_t spin_limit;     // polls a look-back wait makes before it gives up
+  uint32_t fin_max;        // largest job finished in registers (0: jobs go to the LDS path)
+  uint32_t grid_fin;       // workgroups of the register-finishing kernel
   uint32_t pad0;
   uint64_t trace_cap;
 };

@@ -38,11 +38,11 @@ class Tuning(ctypes.Structure):
         ("nontemporal", _u32),
         ("big_rule", _u32),
         ("job_records", _u32),
-        ("reserved", _u32),
+        ("reg_finish", _u32),
     ]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class TraceRow(ctypes.Structure):

@@ -157,6 +157,10 @@ TUNINGS = [
     dict(tile_records=256, big_min=4096),
     dict(tile_records=1024, big_min=2048, workgroups_per_cu=1),
     dict(nontemporal=1, workgroups_per_cu=4),
+    dict(reg_finish=0),
+    dict(reg_finish=0, big_digit_bits=6, job_records=512),
+    dict(reg_finish=1, job_records=4096),
+    dict(reg_finish=1, big_digit_bits=11, tile_records=2048, big_min=4096),
 ]
 
 
@@ -179,3 +183,33 @@ def test_run_twice_identical(R):
     a = gpu_sort(R, host, 8)
     b = gpu_sort(R, host, 8)
     assert np.array_equal(a, b)
+
+
+def _dup_records(keys, r=16):
+    n = len(keys)
+    rec = np.zeros((n, r), dtype=np.uint8)
+    rec[:, 0:8] = np.asarray(keys, dtype="<u8").view(np.uint8).reshape(n, 8)
+    rec[:, 8:16] = np.arange(n, dtype="<u8").view(np.uint8).reshape(n, 8)
+    return rec
+
+
+@pytest.mark.parametrize("case", ["three_keys", "heavy_key", "low_bits", "high_bits", "two_heavy"])
+def test_register_finish_duplicates(R, case, rng):
+    """Jobs of the register-finishing kernel whose digit sub-bins are large
+    (runs of equal keys, few varying bits): the wavefront bitonic network and
+    the binary-search slots, against the oracle."""
+    if case == "three_keys":
+        keys = rng.choice(np.array([5, 1 << 40, (1 << 63) + 7], dtype=np.uint64), 300_000)
+    elif case == "heavy_key":
+        keys = rng.integers(0, 1 << 64, 20_000, dtype=np.uint64)
+        keys[rng.random(20_000) < 0.75] = np.uint64(0x0123456789ABCDEF)
+    elif case == "low_bits":
+        keys = np.uint64(0xABCDEF0000000000) | rng.integers(0, 1 << 9, 200_000, dtype=np.uint64)
+    elif case == "high_bits":
+        keys = rng.integers(0, 1 << 10, 200_000, dtype=np.uint64) << np.uint64(54)
+    else:
+        keys = rng.integers(0, 1 << 64, 16_000, dtype=np.uint64)
+        u = rng.random(16_000)
+        keys[u < 0.4] = np.uint64(3)
+        keys[u > 0.6] = np.uint64(3) + np.uint64(1 << 20)
+    check(R, _dup_records(keys), 8, f"register finish {case} n={len(keys)}")
