@@ -33,7 +33,10 @@ namespace rd {
 
 constexpr int FWG = 1024;              // threads of a finishing workgroup
 constexpr int FWAVES = FWG / 64;
-constexpr uint32_t FSUB = 32;          // larger sub-bins are sorted by a wavefront network
+constexpr uint32_t FSUB = 32;          // larger sub-bins are split or sorted by a wavefront network
+constexpr uint32_t FIN_SPLIT_MAX = 96; // large sub-bins that may be split
+constexpr uint32_t FIN_MINORS = 24;    // records of a split sub-bin outside its run of equal keys
+constexpr uint32_t FIN_POOL = 256;     // pool of those records' composites
 
 template <int RW>
 struct FinShape {
@@ -46,8 +49,15 @@ struct FinShared {
   uint32_t wsum[FWAVES];               // per-wave sums of the counter scan
   uint32_t wmax[FWAVES];
   uint32_t job[2];                     // claimed job index (by iteration parity)
-  uint32_t nbig, bignext;              // sub-bins above FSUB and the next one to sort
+  uint32_t nbig, bignext, npool;       // large sub-bins, the next one to handle, pool fill
   uint32_t big[FIN_LDS_BIG];           // their digits
+  // split large sub-bins (the first FIN_SPLIT_MAX of them)
+  uint64_t bH[FIN_SPLIT_MAX];          // the shared key part
+  uint32_t binfo[FIN_SPLIT_MAX];       // pool offset | minors << 16
+  uint32_t bless[FIN_SPLIT_MAX];       // minors with a smaller key part
+  uint32_t bkind[FIN_LDS_BIG];         // 1: split, 0: sorted by the network
+  uint32_t cw[FWAVES * FIN_SPLIT_MAX]; // H records per wave, then those of earlier waves
+  uint64_t pool[FIN_POOL];             // the minors' composites
 };
 
 // Keeps the scheduler from interleaving the unrolled per-record iterations
@@ -181,52 +191,75 @@ __global__ __launch_bounds__(FWG) void k_fin_jobs(Plan p, Work w, uint8_t* rec0,
   constexpr uint32_t E = FinShape<RW>::E;
   constexpr uint32_t M = FinShape<RW>::M;
   constexpr uint32_t RMAX = 1u << FIN_DIGIT_BITS;
+  constexpr uint32_t RB = 4 * RW;  // record bytes
   extern __shared__ __align__(16) uint32_t dyn[];
   __shared__ FinShared S;
   uint64_t* comp = reinterpret_cast<uint64_t*>(dyn);          // M composites
   uint32_t* cnt = dyn + 2 * M;                                // RMAX + 1 counters
   uint32_t* stage = dyn;                                      // records, while delivering
-  const uint32_t stage_cap = FIN_LDS_BYTES / (4 * RW);
+  const uint32_t stage_cap = FIN_LDS_BYTES / RB;
   const KeyFmt kf = make_keyfmt(p.key_bytes);
   const uint32_t nj = (uint32_t)min((uint64_t)w.ctl->nwg, p.cap_wg);
+
+  // Record q of a job sits in wave q / (64E), slot (q / 64) mod E, lane
+  // q mod 64: each wave holds a contiguous block, loaded 64 records at a
+  // time, so counting in slot order within a wave and then over the waves
+  // follows the input order.
+  Rec<RW> r[E];
+  // The last slice of a job stays in LDS until the next iteration has issued
+  // the loads of its job's records: those loads are then in flight while the
+  // slice is written out.
+  __amdgpu_buffer_rsrc_t pend_dr = job_rsrc(rec0, 0);
+  uint32_t pend_base = 0, pend_cnt = 0;
+  // job claims alternate between two slots: a wave still reading one claim
+  // is never overtaken by the next
+  if (threadIdx.x == 0) S.job[0] = atomicAdd(&w.ctl->wg_head, 1u);
+  __syncthreads();
 
   for (uint32_t it = 0;; it++) {
     uint32_t t = threadIdx.x;
     asm volatile("" : "+v"(t));
     const uint32_t wave = t / 64, lane = t & 63;
-    // the claimed index alternates between two slots: a slow wave still
-    // reading this job's slot is never overtaken by the next claim
-    if (t == 0) S.job[it & 1] = atomicAdd(&w.ctl->wg_head, 1u);
-    for (uint32_t v = t; v <= RMAX; v += FWG) cnt[v] = 0;
-    if (t == 0) { S.nbig = 0; S.bignext = 0; }
-    __syncthreads();
+    const uint32_t q0 = wave * (E * 64) + lane;     // record of slot 0
     const uint32_t idx = uniform32(S.job[it & 1]);
-    if (idx >= nj) break;
-    // every lane reads the same descriptor: keep it in scalar registers
-    const uint64_t jbegin = uniform64(w.wgjobs[idx].begin);
-    const uint32_t m = uniform32((uint32_t)w.wgjobs[idx].count);
-    const uint32_t jflags = uniform32(w.wgjobs[idx].flags);
-    const uint8_t* src = (jflags & BF_TMP) ? rec1 : rec0;
-    uint8_t* dst = rec0;
-    if (t == 0) atomicAdd(&w.ctl->stage_records[2], (unsigned long long)m);
-    if (m > M) {  // the routing never queues such a job; refuse it loudly
-      if (t == 0) atomicOr(&w.ctl->error, 4u);
-      continue;
+    uint64_t jbegin = 0;
+    uint32_t m = 0, jflags = 0;
+    if (idx < nj) {
+      // every lane reads the same descriptor: keep it in scalar registers
+      jbegin = uniform64(w.wgjobs[idx].begin);
+      m = uniform32((uint32_t)w.wgjobs[idx].count);
+      jflags = uniform32(w.wgjobs[idx].flags);
+      if (m <= M) {
+        const uint8_t* src = (jflags & BF_TMP) ? rec1 : rec0;
+        const __amdgpu_buffer_rsrc_t sr = job_rsrc(src + jbegin * RB, m * RB);
+        // offsets past the job read 0
+#pragma unroll
+        for (uint32_t u = 0; u < E; u++) r[u] = buf_load_rec<RW>(sr, q0 * RB, u * 64 * RB);
+      }
     }
-    constexpr uint32_t RB = 4 * RW;  // record bytes
-    const __amdgpu_buffer_rsrc_t sr = job_rsrc(src + jbegin * RB, m * RB);
-    const __amdgpu_buffer_rsrc_t dr = job_rsrc(dst + jbegin * RB, m * RB);
-
-    // records of this thread: slots u < nv.  The count is re-read through an
+    for (uint32_t i = t; i < pend_cnt; i += FWG) buf_store_rec<RW>(pend_dr, i * RB, pend_base * RB, lds_get<RW>(stage, i));
+    pend_cnt = 0;
+    __syncthreads();
+    if (idx >= nj) break;
+    // slots u < nv hold records of the job.  The count is re-read through an
     // empty asm statement at each phase, so that the compiler recomputes the
     // per-slot conditions there instead of holding E lane masks throughout.
-    uint32_t nv = m > t ? min(E, (m - t + FWG - 1) / FWG) : 0u;
-    // 1. the job's records into registers (offsets past the job read 0)
-    Rec<RW> r[E];
-#pragma unroll
-    for (uint32_t u = 0; u < E; u++) r[u] = buf_load_rec<RW>(sr, t * RB, u * FWG * RB);
-    // 2. the bits that vary over the job
-    const uint64_t ref = rec_key<RW>(buf_load_rec<RW>(sr, 0, 0), kf).lo;
+    uint32_t nv = m > q0 ? min(E, (m - q0 + 63) / 64) : 0u;
+    for (uint32_t v = t; v <= RMAX; v += FWG) cnt[v] = 0;
+    if (t == 0) { S.nbig = 0; S.bignext = 0; S.npool = 0; }
+    if (t == 0) atomicAdd(&w.ctl->stage_records[2], (unsigned long long)m);
+    const __amdgpu_buffer_rsrc_t dr = job_rsrc(rec0 + jbegin * RB, m * RB);
+    // the next job is claimed early: every path below passes a barrier
+    // before the next iteration reads the claim
+    if (t == 0) S.job[(it + 1) & 1] = atomicAdd(&w.ctl->wg_head, 1u);
+    if (m > M) {  // the routing never queues such a job; refuse it loudly
+      if (t == 0) atomicOr(&w.ctl->error, 4u);
+      __syncthreads();
+      continue;
+    }
+
+    // the bits that vary over the job
+    const uint64_t ref = uniform64(rec_key<RW>(buf_load_rec<RW>(job_rsrc(((jflags & BF_TMP) ? rec1 : rec0) + jbegin * RB, RB), 0, 0), kf).lo);
     uint64_t vo = 0;
     asm volatile("" : "+v"(nv));
 #pragma unroll
@@ -240,11 +273,13 @@ __global__ __launch_bounds__(FWG) void k_fin_jobs(Plan p, Work w, uint8_t* rec0,
     for (int q = 0; q < FWAVES; q++) vary |= S.wv[q];
     if (vary == 0) {
       // every key equal: the job is in order already
-      if (src != dst) {
+      if (jflags & BF_TMP) {
+        asm volatile("" : "+v"(nv));
 #pragma unroll
         for (uint32_t u = 0; u < E; u++)
-          if (u < nv) buf_store_rec<RW>(dr, t * RB, u * FWG * RB, r[u]);
+          if (u < nv) buf_store_rec<RW>(dr, q0 * RB, u * 64 * RB, r[u]);
       }
+      __syncthreads();
       continue;
     }
     const uint32_t lo = (uint32_t)__builtin_ctzll(vary);
@@ -255,14 +290,15 @@ __global__ __launch_bounds__(FWG) void k_fin_jobs(Plan p, Work w, uint8_t* rec0,
     const uint32_t ib = 32u - __clz(m - 1);          // index bits
     if (rb + ib > 64) {  // the routing never queues such a job
       if (t == 0) atomicOr(&w.ctl->error, 4u);
+      __syncthreads();
       continue;
     }
-    const uint64_t rmask = rb == 0 ? 0ull : (rb >= 64 ? ~0ull : ((1ull << rb) - 1));
+    const uint64_t rmask = rb == 0 ? 0ull : ((1ull << rb) - 1);
     const uint32_t R = 1u << D;
     auto digit_of = [&](uint64_t key) -> uint32_t { return (uint32_t)(key >> dsh) & (R - 1); };
     auto comp_of = [&](uint64_t key, uint32_t q) -> uint64_t { return (((key >> lo) & rmask) << ib) | q; };
 
-    // 3. counting pass: counts, exclusive scan, placement
+    // counting pass: counts, exclusive scan, placement
     asm volatile("" : "+v"(nv));
 #pragma unroll
     for (uint32_t u = 0; u < E; u++)
@@ -291,25 +327,39 @@ __global__ __launch_bounds__(FWG) void k_fin_jobs(Plan p, Work w, uint8_t* rec0,
     asm volatile("" : "+v"(nv));
 #pragma unroll
     for (uint32_t u = 0; u < E; u++) {
-      const uint32_t q = u * FWG + t;
       if (u < nv) {
         const uint64_t key = rec_key<RW>(r[u], kf).lo;
-        comp[atomicAdd(&cnt[digit_of(key)], 1u)] = comp_of(key, q);
+        comp[atomicAdd(&cnt[digit_of(key)], 1u)] = comp_of(key, q0 + 64 * u);
       }
       fin_sched_fence();
     }
     __syncthreads();
-    // cnt[v] is now the end of sub-bin v (and the start of v + 1)
+    // cnt[v] (low 16 bits) is now the end of sub-bin v and the start of v + 1
 
-    // 4a. sub-bins above FSUB: sorted in place, one wavefront each
+    // Sub-bins above FSUB composites.  The usual cause is a run of equal
+    // keys: if all but at most FIN_MINORS of a sub-bin's composites share one
+    // key part H, those "minors" are copied to a pool and the H records are
+    // ranked among themselves in input order (stable counting by sub-bin
+    // below); otherwise one wavefront sorts the sub-bin in place.  The
+    // sub-bin's index among the large ones is kept in the high bits of its
+    // end counter.
+    // slots fit 16 bits (M <= 2^16): two per register.  An H record of a
+    // split sub-bin first keeps its rank among the H records of its wave.
+    uint32_t slot2[(E + 1) / 2];
+#pragma unroll
+    for (uint32_t h = 0; h < (E + 1) / 2; h++) slot2[h] = 0;
     if (bigmax > FSUB) {
       for (uint32_t v = t; v < R; v += FWG) {
-        const uint32_t s0 = v ? cnt[v - 1] : 0u;
+        const uint32_t s0 = v ? (cnt[v - 1] & 0xFFFFu) : 0u;
         if (cnt[v] - s0 > FSUB) {
           const uint32_t i = atomicAdd(&S.nbig, 1u);
-          if (i < FIN_LDS_BIG) S.big[i] = v;
+          if (i < FIN_LDS_BIG) {
+            S.big[i] = v;
+            cnt[v] |= (i + 1) << 16;
+          }
         }
       }
+      for (uint32_t i = t; i < FIN_SPLIT_MAX * FWAVES; i += FWG) S.cw[i] = 0;
       __syncthreads();
       const uint32_t nbig = min(S.nbig, FIN_LDS_BIG);
       for (;;) {
@@ -318,46 +368,143 @@ __global__ __launch_bounds__(FWG) void k_fin_jobs(Plan p, Work w, uint8_t* rec0,
         i = uniform32(i);
         if (i >= nbig) break;
         const uint32_t v = S.big[i];
-        const uint32_t s0 = v ? cnt[v - 1] : 0u;
-        wave_bitonic(comp + s0, cnt[v] - s0, lane);
+        const uint32_t s0 = v ? (cnt[v - 1] & 0xFFFFu) : 0u, e = cnt[v] & 0xFFFFu;
+        uint32_t kind = 0;  // 0: sorted by the network, 1: split
+        if (i < FIN_SPLIT_MAX) {
+          // H: the key part shared by two of three samples, if any
+          const uint64_t k0 = comp[s0] >> ib, k1 = comp[(s0 + e) / 2] >> ib, k2 = comp[e - 1] >> ib;
+          const uint64_t H = (k0 == k1 || k0 == k2) ? k0 : k1;
+          uint32_t nm = 0, nless = 0;
+          for (uint32_t j0 = s0; j0 < e && nm <= FIN_MINORS; j0 += 64) {
+            const uint32_t j = j0 + lane;
+            const uint64_t x = j < e ? comp[j] : 0ull;
+            const bool minor = j < e && (x >> ib) != H;
+            nm += (uint32_t)__popcll(__ballot(minor));
+            nless += (uint32_t)__popcll(__ballot(minor && (x >> ib) < H));
+          }
+          if (nm <= FIN_MINORS) {
+            uint32_t at = 0;
+            if (lane == 0) at = atomicAdd(&S.npool, nm);
+            at = uniform32(at);
+            if (at + nm <= FIN_POOL) {
+              uint32_t put = at;
+              for (uint32_t j0 = s0; j0 < e; j0 += 64) {
+                const uint32_t j = j0 + lane;
+                const uint64_t x = j < e ? comp[j] : 0ull;
+                const bool minor = j < e && (x >> ib) != H;
+                const uint64_t bal = __ballot(minor);
+                if (minor) S.pool[put + (uint32_t)__popcll(bal & lanemask_lt())] = x;
+                put += (uint32_t)__popcll(bal);
+              }
+              if (lane == 0) {
+                S.bH[i] = H;
+                S.binfo[i] = at | (nm << 16);
+                S.bless[i] = nless;
+              }
+              kind = 1;
+            }
+          }
+        }
+        if (lane == 0) S.bkind[i] = kind;
+        if (!kind) wave_bitonic(comp + s0, e - s0, lane);
+      }
+      __syncthreads();
+      // H records of split sub-bins: count them per wave in slot order
+      // (peers of a round found by ballots on the sub-bin index)
+      asm volatile("" : "+v"(nv));
+#pragma unroll
+      for (uint32_t u = 0; u < E; u++) {
+        uint32_t bi = FIN_SPLIT_MAX;
+        if (u < nv) {
+          const uint64_t key = rec_key<RW>(r[u], kf).lo;
+          const uint32_t tag = cnt[digit_of(key)] >> 16;
+          if (tag && tag - 1 < FIN_SPLIT_MAX && S.bkind[tag - 1] == 1 &&
+              ((key >> lo) & rmask) == S.bH[tag - 1] >> 0)
+            bi = tag - 1;
+        }
+        const bool act = bi < FIN_SPLIT_MAX;
+        const uint64_t peers = match_digit_n<7>(bi, __ballot(act));
+        if (act) {
+          const uint32_t leader = (uint32_t)(__ffsll((long long)peers) - 1);
+          uint32_t old = 0;
+          if (leader == lane) old = atomicAdd(&S.cw[wave * FIN_SPLIT_MAX + bi], (uint32_t)__popcll(peers));
+          old = fshfl(old, leader);
+          slot2[u / 2] |= (old + (uint32_t)__popcll(peers & lanemask_lt())) << (16 * (u & 1));
+        }
+        fin_sched_fence();
+      }
+      __syncthreads();
+      // per sub-bin: H records of the earlier waves
+      if (t < FIN_SPLIT_MAX) {
+        uint32_t run = 0;
+#pragma unroll
+        for (uint32_t q = 0; q < FWAVES; q++) {
+          const uint32_t x = S.cw[q * FIN_SPLIT_MAX + t];
+          S.cw[q * FIN_SPLIT_MAX + t] = run;
+          run += x;
+        }
       }
       __syncthreads();
     }
-    // 4b. every record's slot
-    // slots fit 16 bits (M <= 2^16): two per register
-    uint32_t slot2[(E + 1) / 2];
-#pragma unroll
-    for (uint32_t h = 0; h < (E + 1) / 2; h++) slot2[h] = 0;
+    // every record's slot
     asm volatile("" : "+v"(nv));
 #pragma unroll
     for (uint32_t u = 0; u < E; u++) {
-      const uint32_t q = u * FWG + t;
+      const uint32_t q = q0 + 64 * u;
       if (u < nv) {
         const uint64_t key = rec_key<RW>(r[u], kf).lo;
         const uint64_t x = comp_of(key, q);
         const uint32_t v = digit_of(key);
-        const uint32_t s0 = v ? cnt[v - 1] : 0u, e = cnt[v];
+        const uint32_t cv = cnt[v];
+        const uint32_t s0 = v ? (cnt[v - 1] & 0xFFFFu) : 0u, e = cv & 0xFFFFu;
         uint32_t pos;
-        if (e - s0 > FSUB) {
-          // sorted sub-bin: x is in it; lower bound
-          uint32_t a = s0, z = e;
-          while (a < z) {
-            const uint32_t mid = (a + z) >> 1;
-            if (comp[mid] < x) a = mid + 1; else z = mid;
-          }
-          pos = a;
-        } else {
+        if (e - s0 <= FSUB) {
+          // count the smaller composites, two at a time (16-byte reads; the
+          // few words read past the sub-bin are ignored)
           uint32_t below = 0;
-          for (uint32_t i = s0; i < e; i++) below += comp[i] < x ? 1u : 0u;
+          for (uint32_t j = s0 & ~1u; j < e; j += 4) {
+            const uint64_t y0 = comp[j], y1 = comp[j + 1], y2 = comp[j + 2], y3 = comp[j + 3];
+            below += (j >= s0 && y0 < x) ? 1u : 0u;
+            below += (j + 1 < e && y1 < x) ? 1u : 0u;
+            below += (j + 2 < e && y2 < x) ? 1u : 0u;
+            below += (j + 3 < e && y3 < x) ? 1u : 0u;
+          }
           pos = s0 + below;
+        } else {
+          const uint32_t bi = (cv >> 16) - 1;
+          if (S.bkind[bi] == 1) {
+            const uint64_t H = S.bH[bi];
+            const uint32_t info = S.binfo[bi];
+            const uint32_t nm = info >> 16, at = info & 0xFFFFu;
+            const uint64_t xk = (key >> lo) & rmask;
+            if (xk == H) {
+              pos = s0 + S.bless[bi] + S.cw[wave * FIN_SPLIT_MAX + bi] + ((slot2[u / 2] >> (16 * (u & 1))) & 0xFFFFu);
+            } else {
+              uint32_t below = 0;
+              for (uint32_t j = 0; j < nm; j++) below += S.pool[at + j] < x ? 1u : 0u;
+              pos = s0 + below + (H < xk ? (e - s0 - nm) : 0u);
+            }
+          } else {
+            // sorted sub-bin: x is in it; lower bound
+            uint32_t a = s0, z = e;
+            while (a < z) {
+              const uint32_t mid = (a + z) >> 1;
+              if (comp[mid] < x) a = mid + 1; else z = mid;
+            }
+            pos = a;
+          }
         }
-        slot2[u / 2] |= pos << (16 * (u & 1));
+        slot2[u / 2] = (slot2[u / 2] & (0xFFFF0000u >> (16 * (u & 1)))) | (pos << (16 * (u & 1)));
       }
       fin_sched_fence();
     }
+    // out in slot order, stage_cap records per round (the stage overlays
+    // the composites: every wave must be done with them); the last slice is
+    // written out by the next iteration
     __syncthreads();
-    // 5. out in slot order, stage_cap records per round
-    for (uint32_t base = 0; base < m; base += stage_cap) {
+    const uint32_t nround = (m + stage_cap - 1) / stage_cap;
+    for (uint32_t k = 0; k < nround; k++) {
+      const uint32_t base = k * stage_cap;
       asm volatile("" : "+v"(nv));
 #pragma unroll
       for (uint32_t u = 0; u < E; u++) {
@@ -366,8 +513,14 @@ __global__ __launch_bounds__(FWG) void k_fin_jobs(Plan p, Work w, uint8_t* rec0,
       }
       __syncthreads();
       const uint32_t cntr = min(stage_cap, m - base);
-      for (uint32_t i = t; i < cntr; i += FWG) buf_store_rec<RW>(dr, i * RB, base * RB, lds_get<RW>(stage, i));
-      __syncthreads();
+      if (k + 1 == nround) {
+        pend_dr = dr;
+        pend_base = base;
+        pend_cnt = cntr;
+      } else {
+        for (uint32_t i = t; i < cntr; i += FWG) buf_store_rec<RW>(dr, i * RB, base * RB, lds_get<RW>(stage, i));
+        __syncthreads();
+      }
     }
   }
 }
