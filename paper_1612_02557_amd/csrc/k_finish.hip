@@ -146,6 +146,21 @@ __device__ __forceinline__ uint32_t fwave_excl_scan(uint32_t x, uint32_t lane, u
   return inc - x;
 }
 
+// The key of a record held in registers, masked to the key bytes.  Each
+// phase takes the mask through an empty asm statement, so that the masked
+// keys are recomputed per phase (two instructions) rather than held for all
+// E records across the phases.
+template <int RW>
+__device__ __forceinline__ uint64_t fkey(const Rec<RW>& r, uint64_t km) {
+  uint64_t k = r.w[0];
+  if constexpr (RW > 1) k |= (uint64_t)r.w[1] << 32;
+  return k & km;
+}
+__device__ __forceinline__ uint64_t phase_mask(uint64_t km) {
+  asm volatile("" : "+s"(km));
+  return km;
+}
+
 __device__ __forceinline__ uint32_t uniform32(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 __device__ __forceinline__ uint64_t uniform64(uint64_t x) {
   return (uint64_t)uniform32((uint32_t)x) | ((uint64_t)uniform32((uint32_t)(x >> 32)) << 32);
@@ -245,6 +260,7 @@ __global__ __launch_bounds__(FWG) void k_fin_jobs(Plan p, Work w, uint8_t* rec0,
     // empty asm statement at each phase, so that the compiler recomputes the
     // per-slot conditions there instead of holding E lane masks throughout.
     uint32_t nv = m > q0 ? min(E, (m - q0 + 63) / 64) : 0u;
+    uint64_t km = kf.mlo;
     for (uint32_t v = t; v <= RMAX; v += FWG) cnt[v] = 0;
     if (t == 0) { S.nbig = 0; S.bignext = 0; S.npool = 0; }
     if (t == 0) atomicAdd(&w.ctl->stage_records[2], (unsigned long long)m);
@@ -262,9 +278,10 @@ __global__ __launch_bounds__(FWG) void k_fin_jobs(Plan p, Work w, uint8_t* rec0,
     const uint64_t ref = uniform64(rec_key<RW>(buf_load_rec<RW>(job_rsrc(((jflags & BF_TMP) ? rec1 : rec0) + jbegin * RB, RB), 0, 0), kf).lo);
     uint64_t vo = 0;
     asm volatile("" : "+v"(nv));
+    km = phase_mask(kf.mlo);
 #pragma unroll
     for (uint32_t u = 0; u < E; u++)
-      if (u < nv) vo |= rec_key<RW>(r[u], kf).lo ^ ref;
+      if (u < nv) vo |= fkey<RW>(r[u], km) ^ ref;
     vo = fwave_or64(vo, lane);
     if (lane == 0) S.wv[wave] = vo;
     __syncthreads();
@@ -275,6 +292,7 @@ __global__ __launch_bounds__(FWG) void k_fin_jobs(Plan p, Work w, uint8_t* rec0,
       // every key equal: the job is in order already
       if (jflags & BF_TMP) {
         asm volatile("" : "+v"(nv));
+        km = phase_mask(kf.mlo);
 #pragma unroll
         for (uint32_t u = 0; u < E; u++)
           if (u < nv) buf_store_rec<RW>(dr, q0 * RB, u * 64 * RB, r[u]);
@@ -300,9 +318,10 @@ __global__ __launch_bounds__(FWG) void k_fin_jobs(Plan p, Work w, uint8_t* rec0,
 
     // counting pass: counts, exclusive scan, placement
     asm volatile("" : "+v"(nv));
+    km = phase_mask(kf.mlo);
 #pragma unroll
     for (uint32_t u = 0; u < E; u++)
-      if (u < nv) atomicAdd(&cnt[digit_of(rec_key<RW>(r[u], kf).lo)], 1u);
+      if (u < nv) atomicAdd(&cnt[digit_of(fkey<RW>(r[u], km))], 1u);
     __syncthreads();
     {
       // two digits per thread (R <= 2048): scan in registers, then over the
@@ -325,10 +344,11 @@ __global__ __launch_bounds__(FWG) void k_fin_jobs(Plan p, Work w, uint8_t* rec0,
 #pragma unroll
     for (uint32_t q = 0; q < FWAVES; q++) bigmax = max(bigmax, S.wmax[q]);
     asm volatile("" : "+v"(nv));
+    km = phase_mask(kf.mlo);
 #pragma unroll
     for (uint32_t u = 0; u < E; u++) {
       if (u < nv) {
-        const uint64_t key = rec_key<RW>(r[u], kf).lo;
+        const uint64_t key = fkey<RW>(r[u], km);
         comp[atomicAdd(&cnt[digit_of(key)], 1u)] = comp_of(key, q0 + 64 * u);
       }
       fin_sched_fence();
@@ -412,11 +432,12 @@ __global__ __launch_bounds__(FWG) void k_fin_jobs(Plan p, Work w, uint8_t* rec0,
       // H records of split sub-bins: count them per wave in slot order
       // (peers of a round found by ballots on the sub-bin index)
       asm volatile("" : "+v"(nv));
+      km = phase_mask(kf.mlo);
 #pragma unroll
       for (uint32_t u = 0; u < E; u++) {
         uint32_t bi = FIN_SPLIT_MAX;
         if (u < nv) {
-          const uint64_t key = rec_key<RW>(r[u], kf).lo;
+          const uint64_t key = fkey<RW>(r[u], km);
           const uint32_t tag = cnt[digit_of(key)] >> 16;
           if (tag && tag - 1 < FIN_SPLIT_MAX && S.bkind[tag - 1] == 1 &&
               ((key >> lo) & rmask) == S.bH[tag - 1] >> 0)
@@ -448,11 +469,12 @@ __global__ __launch_bounds__(FWG) void k_fin_jobs(Plan p, Work w, uint8_t* rec0,
     }
     // every record's slot
     asm volatile("" : "+v"(nv));
+    km = phase_mask(kf.mlo);
 #pragma unroll
     for (uint32_t u = 0; u < E; u++) {
       const uint32_t q = q0 + 64 * u;
       if (u < nv) {
-        const uint64_t key = rec_key<RW>(r[u], kf).lo;
+        const uint64_t key = fkey<RW>(r[u], km);
         const uint64_t x = comp_of(key, q);
         const uint32_t v = digit_of(key);
         const uint32_t cv = cnt[v];
@@ -506,6 +528,7 @@ __global__ __launch_bounds__(FWG) void k_fin_jobs(Plan p, Work w, uint8_t* rec0,
     for (uint32_t k = 0; k < nround; k++) {
       const uint32_t base = k * stage_cap;
       asm volatile("" : "+v"(nv));
+      km = phase_mask(kf.mlo);
 #pragma unroll
       for (uint32_t u = 0; u < E; u++) {
         const uint32_t o = ((slot2[u / 2] >> (16 * (u & 1))) & 0xFFFFu) - base;
