@@ -214,7 +214,7 @@ Plan make_plan(uint64_t n, uint32_t r, uint32_t k, const raduls_tuning& t, int c
   p.grid_fin = cus;
   const int lds_limit = device_lds_per_block();
   if (allow_fin && t.reg_finish && k <= 8 && g_sched_mode == RADULS_SCHED_HEURISTIC &&
-      (lds_limit <= 0 || lds_limit >= (int)(rd::FIN_LDS_BYTES + 4096))) {
+      (lds_limit <= 0 || lds_limit >= (int)(rd::FIN_LDS_BYTES + rd::FIN_STATIC_LDS))) {
     p.fin_max = rd::fin_records_per_thread(p.rw) * rd::FIN_THREADS;
     p.t_big = std::max<uint64_t>(t.big_min, (uint64_t)p.fin_max);
     const uint32_t fjob = t.job_records ? std::min<uint32_t>(std::max<uint32_t>(t.job_records, p.c_fin), p.fin_max)

@@ -34,9 +34,10 @@ namespace rd {
 constexpr int FWG = 1024;              // threads of a finishing workgroup
 constexpr int FWAVES = FWG / 64;
 constexpr uint32_t FSUB = 32;          // larger sub-bins are split or sorted by a wavefront network
-constexpr uint32_t FIN_SPLIT_MAX = 96; // large sub-bins that may be split
+constexpr uint32_t FIN_SPLIT_MAX = 64; // large sub-bins that may be split
 constexpr uint32_t FIN_MINORS = 24;    // records of a split sub-bin outside its run of equal keys
-constexpr uint32_t FIN_POOL = 256;     // pool of those records' composites
+constexpr uint32_t FIN_POOL_WAVE = 32; // pool of those records' composites, per wave
+constexpr uint32_t FIN_POOL = FIN_POOL_WAVE * FWAVES;
 
 template <int RW>
 struct FinShape {
@@ -49,16 +50,23 @@ struct FinShared {
   uint32_t wsum[FWAVES];               // per-wave sums of the counter scan
   uint32_t wmax[FWAVES];
   uint32_t job[2];                     // claimed job index (by iteration parity)
-  uint32_t nbig, bignext, npool;       // large sub-bins, the next one to handle, pool fill
-  uint32_t big[FIN_LDS_BIG];           // their digits
-  // split large sub-bins (the first FIN_SPLIT_MAX of them)
+  uint32_t nbig;                       // large sub-bins
+  uint32_t ntop;                       // distinct top-8-bit values of a grouped job
+  uint16_t big[FIN_LDS_BIG];           // digits of the large sub-bins
+  uint8_t rank8[256];                  // grouped job: rank of a top-8-bit value among those present
+  uint8_t btag[1u << FIN_DIGIT_BITS];  // sub-bin -> 1 + its index among the split ones, or 0
+  // split large sub-bins (the first FIN_SPLIT_MAX of them in digit order)
   uint64_t bH[FIN_SPLIT_MAX];          // the shared key part
   uint32_t binfo[FIN_SPLIT_MAX];       // pool offset | minors << 16
   uint32_t bless[FIN_SPLIT_MAX];       // minors with a smaller key part
-  uint32_t bkind[FIN_LDS_BIG];         // 1: split, 0: sorted by the network
-  uint32_t cw[FWAVES * FIN_SPLIT_MAX]; // H records per wave, then those of earlier waves
+  union {
+    uint32_t h8[256];                  // grouped job: counts of the top 8 varying bits
+    uint32_t cw[FWAVES * FIN_SPLIT_MAX];  // H records per wave, then those of earlier waves
+  };
   uint64_t pool[FIN_POOL];             // the minors' composites
 };
+
+static_assert(sizeof(FinShared) <= FIN_STATIC_LDS, "static LDS of the finishing kernel");
 
 // Keeps the scheduler from interleaving the unrolled per-record iterations
 // (that would hold every iteration's temporaries at once and spill).
@@ -176,7 +184,8 @@ __device__ __forceinline__ void fin_wave_sync() {
 // at the lower index, so they never move and are never touched.  Each
 // merge phase of block size k starts by comparing an element with its
 // mirror in the block, then halves the distance down to 1.
-__device__ __forceinline__ void wave_bitonic(uint64_t* c, uint32_t s, uint32_t lane) {
+template <typename T>
+__device__ __forceinline__ void wave_bitonic(T* c, uint32_t s, uint32_t lane) {
   uint32_t P = 1;
   while (P < s) P <<= 1;
   for (uint32_t k = 2; k <= P; k <<= 1) {
@@ -192,7 +201,7 @@ __device__ __forceinline__ void wave_bitonic(uint64_t* c, uint32_t s, uint32_t l
           b = a + j;
         }
         if (b < s) {
-          const uint64_t x = c[a], y = c[b];
+          const T x = c[a], y = c[b];
           if (x > y) { c[a] = y; c[b] = x; }
         }
       }
@@ -206,15 +215,16 @@ __global__ __launch_bounds__(FWG) void k_fin_jobs(Plan p, Work w, uint8_t* rec0,
   constexpr uint32_t E = FinShape<RW>::E;
   constexpr uint32_t M = FinShape<RW>::M;
   constexpr uint32_t RMAX = 1u << FIN_DIGIT_BITS;
+  constexpr uint32_t NCW = RMAX / 2 + 1;  // counter words: two 16-bit counters each
   constexpr uint32_t RB = 4 * RW;  // record bytes
   extern __shared__ __align__(16) uint32_t dyn[];
   __shared__ FinShared S;
   uint64_t* comp = reinterpret_cast<uint64_t*>(dyn);          // M composites
-  uint32_t* cnt = dyn + 2 * M;                                // RMAX + 1 counters
+  uint32_t* cnt = dyn + 2 * M;                                // NCW words of packed counters
   uint32_t* stage = dyn;                                      // records, while delivering
   const uint32_t stage_cap = FIN_LDS_BYTES / RB;
   const KeyFmt kf = make_keyfmt(p.key_bytes);
-  const uint32_t nj = (uint32_t)min((uint64_t)w.ctl->nwg, p.cap_wg);
+  const uint32_t nj = uniform32((uint32_t)min((uint64_t)w.ctl->nwg, p.cap_wg));
 
   // Record q of a job sits in wave q / (64E), slot (q / 64) mod E, lane
   // q mod 64: each wave holds a contiguous block, loaded 64 records at a
@@ -261,8 +271,9 @@ __global__ __launch_bounds__(FWG) void k_fin_jobs(Plan p, Work w, uint8_t* rec0,
     // per-slot conditions there instead of holding E lane masks throughout.
     uint32_t nv = m > q0 ? min(E, (m - q0 + 63) / 64) : 0u;
     uint64_t km = kf.mlo;
-    for (uint32_t v = t; v <= RMAX; v += FWG) cnt[v] = 0;
-    if (t == 0) { S.nbig = 0; S.bignext = 0; S.npool = 0; }
+    for (uint32_t v = t; v < NCW; v += FWG) cnt[v] = 0;
+    for (uint32_t v = t; v < 256; v += FWG) S.h8[v] = 0;
+    if (t == 0) S.nbig = 0;
     if (t == 0) atomicAdd(&w.ctl->stage_records[2], (unsigned long long)m);
     const __amdgpu_buffer_rsrc_t dr = job_rsrc(rec0 + jbegin * RB, m * RB);
     // the next job is claimed early: every path below passes a barrier
@@ -302,8 +313,41 @@ __global__ __launch_bounds__(FWG) void k_fin_jobs(Plan p, Work w, uint8_t* rec0,
     }
     const uint32_t lo = (uint32_t)__builtin_ctzll(vary);
     const uint32_t hi = 64u - (uint32_t)__clzll(vary);
-    const uint32_t D = min(FIN_DIGIT_BITS, hi - lo);
-    const uint32_t dsh = hi - D;
+    const uint32_t W = hi - lo;
+    // The digit is the top D <= 12 varying bits.  A job grouped from
+    // consecutive children holds only a few values of their parent's digit
+    // in its top bits, so there the digit is the rank of the top 8 varying
+    // bits among the values present, followed by as many lower bits as fit.
+    const bool grouped = (jflags & BF_GROUP) && W > FIN_DIGIT_BITS;
+    const uint32_t sh8 = hi >= 8 ? hi - 8 : 0;
+    uint32_t xb = 0;  // lower bits after the rank (grouped jobs)
+    if (grouped) {
+      asm volatile("" : "+v"(nv));
+      km = phase_mask(kf.mlo);
+#pragma unroll
+      for (uint32_t u = 0; u < E; u++)
+        if (u < nv) atomicAdd(&S.h8[(uint32_t)(fkey<RW>(r[u], km) >> sh8) & 255u], 1u);
+      __syncthreads();
+      if (wave == 0) {
+        uint32_t pres = 0;
+#pragma unroll
+        for (uint32_t k = 0; k < 4; k++) pres |= (S.h8[4 * lane + k] ? 1u : 0u) << k;
+        uint32_t tot;
+        uint32_t ex = fwave_excl_scan((uint32_t)__popc(pres), lane, &tot);
+#pragma unroll
+        for (uint32_t k = 0; k < 4; k++) {
+          S.rank8[4 * lane + k] = (uint8_t)ex;
+          ex += (pres >> k) & 1u;
+        }
+        if (lane == 0) S.ntop = tot;
+      }
+      __syncthreads();
+      const uint32_t c = S.ntop;  // at least 2: the top varying bit takes both values
+      const uint32_t cb = 32u - __clz(c - 1);
+      xb = min(FIN_DIGIT_BITS - cb, W - 8);
+    }
+    const uint32_t D = grouped ? (32u - __clz(S.ntop - 1)) + xb : min(FIN_DIGIT_BITS, W);
+    const uint32_t dsh = grouped ? sh8 - xb : hi - D;  // lowest bit of the digit's key bits
     const uint32_t rb = dsh - lo;                    // key bits below the digit
     const uint32_t ib = 32u - __clz(m - 1);          // index bits
     if (rb + ib > 64) {  // the routing never queues such a job
@@ -313,31 +357,45 @@ __global__ __launch_bounds__(FWG) void k_fin_jobs(Plan p, Work w, uint8_t* rec0,
     }
     const uint64_t rmask = rb == 0 ? 0ull : ((1ull << rb) - 1);
     const uint32_t R = 1u << D;
-    auto digit_of = [&](uint64_t key) -> uint32_t { return (uint32_t)(key >> dsh) & (R - 1); };
+    const uint32_t xmask = (1u << xb) - 1u;
+    auto digit_of = [&](uint64_t key) -> uint32_t {
+      if (grouped) return ((uint32_t)S.rank8[(uint32_t)(key >> sh8) & 255u] << xb) | ((uint32_t)(key >> dsh) & xmask);
+      return (uint32_t)(key >> dsh) & (R - 1);
+    };
     auto comp_of = [&](uint64_t key, uint32_t q) -> uint64_t { return (((key >> lo) & rmask) << ib) | q; };
+    // sub-bin v occupies [end(v - 1), end(v)) once the placement is done
+    auto cnt_end = [&](uint32_t v) -> uint32_t { return (cnt[v >> 1] >> (16 * (v & 1))) & 0xFFFFu; };
+    auto cnt_start = [&](uint32_t v) -> uint32_t { return v ? cnt_end(v - 1) : 0u; };
 
-    // counting pass: counts, exclusive scan, placement
+    // counting pass: counts, exclusive scan, placement (16-bit counters,
+    // two per word: no count exceeds M < 2^16)
     asm volatile("" : "+v"(nv));
     km = phase_mask(kf.mlo);
 #pragma unroll
     for (uint32_t u = 0; u < E; u++)
-      if (u < nv) atomicAdd(&cnt[digit_of(fkey<RW>(r[u], km))], 1u);
+      if (u < nv) {
+        const uint32_t v = digit_of(fkey<RW>(r[u], km));
+        atomicAdd(&cnt[v >> 1], 1u << (16 * (v & 1)));
+      }
     __syncthreads();
     {
-      // two digits per thread (R <= 2048): scan in registers, then over the
-      // waves through LDS; the largest count is found on the way
-      const uint32_t v0 = 2 * t;
-      const uint32_t a = v0 < R ? cnt[v0] : 0u, c = v0 + 1 < R ? cnt[v0 + 1] : 0u;
+      // four digits (two words) per thread (R <= 4096): scan in registers,
+      // then over the waves through LDS; the largest count on the way
+      const uint32_t nw = R / 2;  // R >= 2
+      const uint32_t w0 = 2 * t < nw ? cnt[2 * t] : 0u;
+      const uint32_t w1 = 2 * t + 1 < nw ? cnt[2 * t + 1] : 0u;
+      const uint32_t a0 = w0 & 0xFFFFu, a1 = w0 >> 16, a2 = w1 & 0xFFFFu, a3 = w1 >> 16;
       uint32_t wt;
-      const uint32_t ex = fwave_excl_scan(a + c, lane, &wt);
-      const uint32_t mx = fwave_max(max(a, c), lane);
+      const uint32_t ex = fwave_excl_scan(a0 + a1 + a2 + a3, lane, &wt);
+      const uint32_t mx = fwave_max(max(max(a0, a1), max(a2, a3)), lane);
       if (lane == 0) { S.wsum[wave] = wt; S.wmax[wave] = mx; }
       __syncthreads();
       uint32_t base = 0;
 #pragma unroll
       for (uint32_t q = 0; q < FWAVES; q++) base += q < wave ? S.wsum[q] : 0u;
-      if (v0 < R) cnt[v0] = base + ex;
-      if (v0 + 1 < R) cnt[v0 + 1] = base + ex + a;
+      const uint32_t s0 = base + ex, s1 = s0 + a0, s2 = s1 + a1, s3 = s2 + a2;
+      if (2 * t < nw) cnt[2 * t] = s0 | (s1 << 16);
+      if (2 * t + 1 < nw) cnt[2 * t + 1] = s2 | (s3 << 16);
     }
     __syncthreads();
     uint32_t bigmax = 0;
@@ -349,20 +407,21 @@ __global__ __launch_bounds__(FWG) void k_fin_jobs(Plan p, Work w, uint8_t* rec0,
     for (uint32_t u = 0; u < E; u++) {
       if (u < nv) {
         const uint64_t key = fkey<RW>(r[u], km);
-        comp[atomicAdd(&cnt[digit_of(key)], 1u)] = comp_of(key, q0 + 64 * u);
+        const uint32_t v = digit_of(key);
+        const uint32_t sh = 16 * (v & 1);
+        const uint32_t pos = (atomicAdd(&cnt[v >> 1], 1u << sh) >> sh) & 0xFFFFu;
+        comp[pos] = comp_of(key, q0 + 64 * u);
       }
       fin_sched_fence();
     }
     __syncthreads();
-    // cnt[v] (low 16 bits) is now the end of sub-bin v and the start of v + 1
 
     // Sub-bins above FSUB composites.  The usual cause is a run of equal
     // keys: if all but at most FIN_MINORS of a sub-bin's composites share one
     // key part H, those "minors" are copied to a pool and the H records are
     // ranked among themselves in input order (stable counting by sub-bin
-    // below); otherwise one wavefront sorts the sub-bin in place.  The
-    // sub-bin's index among the large ones is kept in the high bits of its
-    // end counter.
+    // below); otherwise one wavefront sorts the sub-bin in place.  Split
+    // sub-bins are tagged in btag.
     // slots fit 16 bits (M <= 2^16): two per register.  An H record of a
     // split sub-bin first keeps its rank among the H records of its wave.
     uint32_t slot2[(E + 1) / 2];
@@ -370,25 +429,25 @@ __global__ __launch_bounds__(FWG) void k_fin_jobs(Plan p, Work w, uint8_t* rec0,
     for (uint32_t h = 0; h < (E + 1) / 2; h++) slot2[h] = 0;
     if (bigmax > FSUB) {
       for (uint32_t v = t; v < R; v += FWG) {
-        const uint32_t s0 = v ? (cnt[v - 1] & 0xFFFFu) : 0u;
-        if (cnt[v] - s0 > FSUB) {
+        if (cnt_end(v) - cnt_start(v) > FSUB) {
           const uint32_t i = atomicAdd(&S.nbig, 1u);
-          if (i < FIN_LDS_BIG) {
-            S.big[i] = v;
-            cnt[v] |= (i + 1) << 16;
-          }
+          if (i < FIN_LDS_BIG) S.big[i] = (uint16_t)v;
         }
       }
+      for (uint32_t i = t; i < (1u << FIN_DIGIT_BITS) / 4; i += FWG) reinterpret_cast<uint32_t*>(S.btag)[i] = 0;
       for (uint32_t i = t; i < FIN_SPLIT_MAX * FWAVES; i += FWG) S.cw[i] = 0;
       __syncthreads();
-      const uint32_t nbig = min(S.nbig, FIN_LDS_BIG);
-      for (;;) {
-        uint32_t i = 0;
-        if (lane == 0) i = atomicAdd(&S.bignext, 1u);
-        i = uniform32(i);
-        if (i >= nbig) break;
-        const uint32_t v = S.big[i];
-        const uint32_t s0 = v ? (cnt[v - 1] & 0xFFFFu) : 0u, e = cnt[v] & 0xFFFFu;
+      // Large sub-bin i goes to wave i mod FWAVES.  The bounds are scalar
+      // (the same LDS word in every lane), so the loop cannot split a wave:
+      // a claim made by one lane and broadcast with readfirstlane, against a
+      // bound held per lane, let the compiler send lane 0 out of the loop
+      // while the other lanes read a stale claim and looped forever.
+      const uint32_t nbig = uniform32(min(S.nbig, FIN_LDS_BIG));
+      const uint32_t wv = uniform32(wave);
+      uint32_t pool_used = 0;  // this wave's part of the pool: [wv * FIN_POOL_WAVE, +FIN_POOL_WAVE)
+      for (uint32_t i = wv; i < nbig; i += FWAVES) {
+        const uint32_t v = uniform32(S.big[i]);
+        const uint32_t s0 = uniform32(cnt_start(v)), e = uniform32(cnt_end(v));
         uint32_t kind = 0;  // 0: sorted by the network, 1: split
         if (i < FIN_SPLIT_MAX) {
           // H: the key part shared by two of three samples, if any
@@ -402,11 +461,10 @@ __global__ __launch_bounds__(FWG) void k_fin_jobs(Plan p, Work w, uint8_t* rec0,
             nm += (uint32_t)__popcll(__ballot(minor));
             nless += (uint32_t)__popcll(__ballot(minor && (x >> ib) < H));
           }
-          if (nm <= FIN_MINORS) {
-            uint32_t at = 0;
-            if (lane == 0) at = atomicAdd(&S.npool, nm);
-            at = uniform32(at);
-            if (at + nm <= FIN_POOL) {
+          if (nm <= FIN_MINORS && pool_used + nm <= FIN_POOL_WAVE) {
+            const uint32_t at = wv * FIN_POOL_WAVE + pool_used;
+            pool_used += nm;
+            {
               uint32_t put = at;
               for (uint32_t j0 = s0; j0 < e; j0 += 64) {
                 const uint32_t j = j0 + lane;
@@ -420,12 +478,12 @@ __global__ __launch_bounds__(FWG) void k_fin_jobs(Plan p, Work w, uint8_t* rec0,
                 S.bH[i] = H;
                 S.binfo[i] = at | (nm << 16);
                 S.bless[i] = nless;
+                S.btag[v] = (uint8_t)(i + 1);
               }
               kind = 1;
             }
           }
         }
-        if (lane == 0) S.bkind[i] = kind;
         if (!kind) wave_bitonic(comp + s0, e - s0, lane);
       }
       __syncthreads();
@@ -438,10 +496,8 @@ __global__ __launch_bounds__(FWG) void k_fin_jobs(Plan p, Work w, uint8_t* rec0,
         uint32_t bi = FIN_SPLIT_MAX;
         if (u < nv) {
           const uint64_t key = fkey<RW>(r[u], km);
-          const uint32_t tag = cnt[digit_of(key)] >> 16;
-          if (tag && tag - 1 < FIN_SPLIT_MAX && S.bkind[tag - 1] == 1 &&
-              ((key >> lo) & rmask) == S.bH[tag - 1] >> 0)
-            bi = tag - 1;
+          const uint32_t tag = S.btag[digit_of(key)];
+          if (tag && ((key >> lo) & rmask) == S.bH[tag - 1]) bi = tag - 1;
         }
         const bool act = bi < FIN_SPLIT_MAX;
         const uint64_t peers = match_digit_n<7>(bi, __ballot(act));
@@ -477,8 +533,7 @@ __global__ __launch_bounds__(FWG) void k_fin_jobs(Plan p, Work w, uint8_t* rec0,
         const uint64_t key = fkey<RW>(r[u], km);
         const uint64_t x = comp_of(key, q);
         const uint32_t v = digit_of(key);
-        const uint32_t cv = cnt[v];
-        const uint32_t s0 = v ? (cnt[v - 1] & 0xFFFFu) : 0u, e = cv & 0xFFFFu;
+        const uint32_t s0 = cnt_start(v), e = cnt_end(v);
         uint32_t pos;
         if (e - s0 <= FSUB) {
           // count the smaller composites, two at a time (16-byte reads; the
@@ -493,8 +548,9 @@ __global__ __launch_bounds__(FWG) void k_fin_jobs(Plan p, Work w, uint8_t* rec0,
           }
           pos = s0 + below;
         } else {
-          const uint32_t bi = (cv >> 16) - 1;
-          if (S.bkind[bi] == 1) {
+          const uint32_t tag = S.btag[v];
+          if (tag) {
+            const uint32_t bi = tag - 1;
             const uint64_t H = S.bH[bi];
             const uint32_t info = S.binfo[bi];
             const uint32_t nm = info >> 16, at = info & 0xFFFFu;

@@ -1145,7 +1145,7 @@ __device__ __forceinline__ void build_jobs(Ctx& c) {
     const uint32_t ib = 32 - __clz(m > 1 ? m - 1 : 1);
     if (m > C && c.p.fin_max && job_ok(c.p, m, bit, KB)) {
       uint32_t i = atomicAdd(&c.w.ctl->nwg, 1u);
-      if (i < c.p.cap_wg) c.w.wgjobs[i] = Bucket{S.cbegin + js, m, parent, bit, ctmp ? BF_TMP : 0u};
+      if (i < c.p.cap_wg) c.w.wgjobs[i] = Bucket{S.cbegin + js, m, parent, bit, (ctmp ? BF_TMP : 0u) | (bit == pb ? BF_GROUP : 0u)};
       else atomicOr(&c.w.ctl->overflow, 32u);
       continue;
     }
@@ -1171,7 +1171,7 @@ __device__ __forceinline__ void build_jobs(Ctx& c) {
       continue;
     }
     uint32_t i = atomicAdd(&c.w.ctl->nwg, 1u);
-    if (i < c.p.cap_wg) c.w.wgjobs[i] = Bucket{S.cbegin + js, m, parent, bit, ctmp ? BF_TMP : 0u};
+    if (i < c.p.cap_wg) c.w.wgjobs[i] = Bucket{S.cbegin + js, m, parent, bit, (ctmp ? BF_TMP : 0u) | (bit == pb ? BF_GROUP : 0u)};
     else atomicOr(&c.w.ctl->overflow, 32u);
   }
   __syncthreads();
@@ -1187,14 +1187,19 @@ __device__ __forceinline__ void run_wave_jobs(Ctx& c) {
   const uint32_t WSC = c.p.wave_cap;
   const uint32_t wave = threadIdx.x / 64;
   uint32_t* reg = c.dyn + wave * (WSC * RW + 4 * WSC + RB);
-  const uint32_t nw = S.nw;
+  // The claim loops below keep their bounds and claims in scalar registers
+  // (readfirstlane of values every lane holds alike), so the loop exit is
+  // uniform and the compiler cannot split a wave across iterations: with a
+  // per-lane bound it may send lane 0 (the one that claims) out of the loop
+  // while the other lanes keep reading a stale claim.
+  const uint32_t nw = __builtin_amdgcn_readfirstlane(S.nw);
   const bool ctmp = S.ctmp != 0;
   const uint64_t base = S.cbegin;
   const uint64_t parent = S.cparent;
   for (;;) {
     uint32_t i = 0;
     if (lane_id() == 0) i = atomicAdd(&S.wnext, 1u);
-    i = __shfl(i, 0);
+    i = __builtin_amdgcn_readfirstlane(__shfl(i, 0));
     if (i >= nw) break;
     const uint32_t m = S.jn[i];
     const uint32_t info = S.jinfo[i];
@@ -1314,11 +1319,12 @@ __global__ __launch_bounds__(WG) void k_small(Plan p, Work w, uint8_t* rec0, uin
     }
   }
   // tiny buckets, one wavefront each
-  const uint32_t nt = (uint32_t)min((uint64_t)w.ctl->ntiny, p.cap_tiny);
+  // scalar bound and claim, as in run_wave_jobs
+  const uint32_t nt = __builtin_amdgcn_readfirstlane((uint32_t)min((uint64_t)w.ctl->ntiny, p.cap_tiny));
   for (;;) {
     uint32_t j = 0;
     if (lane_id() == 0) j = atomicAdd(&w.ctl->tiny_head, 1u);
-    j = __shfl(j, 0);
+    j = __builtin_amdgcn_readfirstlane(__shfl(j, 0));
     if (j >= nt) break;
     uint64_t x = w.tiny[j];
     uint64_t begin = x & ((1ull << 40) - 1);

@@ -17,6 +17,7 @@ struct Bucket {
 constexpr uint32_t BF_TMP = 1u;
 constexpr uint32_t BF_SKIP = 2u;
 constexpr uint32_t BF_ROOT = 4u;  // deferred job that is a queued bucket (one more radix pass allowed)
+constexpr uint32_t BF_GROUP = 8u; // finishing job made of several consecutive children
 
 constexpr uint32_t LMAX = 20;        // multi-workgroup levels a plan may launch
 constexpr uint32_t TSCAN_CH = 32;    // tiles per chunk of the tile-offset scan
@@ -28,12 +29,14 @@ constexpr uint32_t NCLASS = 40;      // size classes of the queued buckets (floo
 // holds fin_records_per_thread(rw) records per thread (at most 68 words),
 // sorts composites of (key bits below an 11-bit digit, index) in LDS.
 constexpr uint32_t FIN_THREADS = 1024;
-constexpr uint32_t FIN_DIGIT_BITS = 11;
+constexpr uint32_t FIN_DIGIT_BITS = 12;
 __host__ __device__ constexpr uint32_t fin_records_per_thread(uint32_t rw) { return 68 / rw < 17 ? 68 / rw : 17; }
 constexpr uint32_t FIN_MAX_RECORDS = 17 * FIN_THREADS;
-constexpr uint32_t FIN_LDS_BYTES = 147712;  // composites of the largest job and 2^11 + 1 counters
+constexpr uint32_t FIN_LDS_BYTES = 147712;  // composites of the largest job and 2^12 16-bit counters
 constexpr uint32_t FIN_LDS_BIG = 544;       // > FIN_MAX_RECORDS / 33: sub-bins above 32 records
-static_assert(FIN_LDS_BYTES >= 8 * FIN_MAX_RECORDS + 4 * ((1u << FIN_DIGIT_BITS) + 1), "LDS of a finishing job");
+constexpr uint32_t FIN_STATIC_LDS = 15360;  // upper bound of the kernel's static LDS
+static_assert(FIN_LDS_BYTES >= 8 * FIN_MAX_RECORDS + 4 * ((1u << FIN_DIGIT_BITS) / 2 + 1), "LDS of a finishing job");
+static_assert(FIN_MAX_RECORDS < 65536, "16-bit counters and slots");
 
 // Device control block: list sizes, tickets, flags.  Cleared at the start of
 // every sort by the init kernel.
