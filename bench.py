@@ -73,25 +73,57 @@ def load_traffic(kernel: str, workload: str):
     return e.get("bytes_per_launch")
 
 
-def cpu_baseline(pristine, key_bytes: int, sample_log2: int):
+def host_description():
+    """CPU model, logical CPUs and RAM of the host, from /proc."""
+    model, ram = "unknown", None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal"):
+                    ram = int(line.split()[1]) * 1024
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "ram_bytes": ram}
+
+
+def cpu_baseline(pristine, key_bytes: int, sample_log2: int, single_log2: int):
+    """The oracle (stable LSD byte-wise counting sort) on the host: threaded
+    on the first 2^sample_log2 records, single-threaded on the first
+    2^single_log2 records of the same input."""
     import numpy as np
 
     import oracle
-    ns = min(pristine.shape[0], 1 << sample_log2)
-    host = pristine[:ns].cpu().numpy().copy()
+    oracle.lib()
     cores = os.cpu_count() or 1
     env = os.environ.get("OMP_NUM_THREADS")
     if env and env.isdigit():
         cores = max(1, min(cores, int(env)))
-    oracle.lib()
-    t0 = time.perf_counter()
-    oracle.sort_ref.sort_inplace(host, key_bytes, cores)
-    dt = time.perf_counter() - t0
-    k = host[:, :8].copy().view("<u8").ravel()
-    assert bool(np.all(k[:-1] <= k[1:])), "oracle output not sorted"
+
+    def run(ns, threads):
+        host = pristine[:ns].cpu().numpy().copy()
+        t0 = time.perf_counter()
+        oracle.sort_ref.sort_inplace(host, key_bytes, threads)
+        dt = time.perf_counter() - t0
+        k = host[:, :8].copy().view("<u8").ravel()
+        assert bool(np.all(k[:-1] <= k[1:])), "oracle output not sorted"
+        return dt
+
+    ns = min(pristine.shape[0], 1 << sample_log2)
+    dt = run(ns, cores)
+    n1 = min(pristine.shape[0], 1 << single_log2)
+    dt1 = run(n1, 1)
     return {"value": ns / dt, "unit": "records/s", "cores": cores, "kind": "oracle",
             "sample": f"first 2^{sample_log2} records of the benchmark input, stable LSD byte-wise counting sort "
-                      f"in {cores} threads, {dt:.2f} s wall"}
+                      f"in {cores} threads, {dt:.2f} s wall",
+            "single_thread": {"value": n1 / dt1, "unit": "records/s", "cores": 1,
+                              "sample": f"first 2^{single_log2} records, one thread, {dt1:.2f} s wall"},
+            "host": host_description()}
 
 
 def batched_check(rec, off, sizes, dists, spec, scratch, S):
@@ -207,6 +239,7 @@ def main():
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-sample-log2", type=int, default=28)
+    ap.add_argument("--cpu-single-log2", type=int, default=25)
     ap.add_argument("--phases", type=int, default=1, help="1: per-phase events during the timed steps")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-scheduler leg")
     ap.add_argument("--tuning", default="", help="tuning overrides, e.g. big_min=8192,workgroups_per_cu=3")
@@ -290,12 +323,12 @@ def main():
     # per-pass algorithmic bytes and rates
     passes = []
     for l, (n_in, n_moved) in enumerate(work["levels"]):
-        for kind, recs, mult in (("hist", n_in, 1), ("scatter", n_moved, 2)):
+        for kind, kern, recs, mult in (("hist", "k_hist_wave", n_in, 1), ("scatter", "k_scatter", n_moved, 2)):
             name = f"L{l}.{kind}"
             if name in phase_acc:
                 t = statistics.mean(phase_acc[name])
                 b = mult * r * recs
-                passes.append({"phase": name, "kernel": f"k_{kind}", "ms": t, "records": recs, "alg_bytes": b,
+                passes.append({"phase": name, "kernel": kern, "ms": t, "records": recs, "alg_bytes": b,
                                "GBps": b / t / 1e6 if t > 0 else None})
     # single-workgroup queue pass: a one-workgroup radix pass reads its bucket
     # twice (count, move) and writes it once; wavefront and tiny jobs read
@@ -310,20 +343,35 @@ def main():
         t = statistics.mean(phase_acc["small_jobs"])
         recs = work["wg_jobs"]
         b = 2 * r * recs
-        passes.append({"phase": "small_jobs", "kernel": "k_small_jobs", "ms": t, "records": recs, "alg_bytes": b,
+        kern = "k_fin_jobs" if work.get("fin_max") else "k_small_jobs"
+        passes.append({"phase": "small_jobs", "kernel": kern, "ms": t, "records": recs, "alg_bytes": b,
                        "GBps": b / t / 1e6 if t > 0 else None})
     other = {nm: statistics.mean(v) for nm, v in phase_acc.items()
              if not any(p["phase"] == nm for p in passes)}
 
+    # per kernel: launches, time per step, algorithmic bytes; the dominant
+    # kernel is the one with the most time per step (all its launches)
+    kernels = {}
+    for p_ in passes:
+        if not p_["ms"] or p_["records"] == 0:
+            continue
+        k_ = kernels.setdefault(p_["kernel"], {"launches": 0, "ms": 0.0, "alg_bytes": 0})
+        k_["launches"] += 1
+        k_["ms"] += p_["ms"]
+        k_["alg_bytes"] += p_["alg_bytes"]
+    for name, k_ in kernels.items():
+        k_["avg_launch_ms"] = k_["ms"] / k_["launches"]
+        k_["alg_bytes_per_launch"] = k_["alg_bytes"] / k_["launches"]
+        k_["GBps"] = k_["alg_bytes"] / k_["ms"] / 1e6
     roof = None
-    if passes:
-        dom = max(passes, key=lambda p: p["ms"])
+    if kernels:
+        dn, dom = max(kernels.items(), key=lambda kv: kv[1]["ms"])
         wl = f"{args.dist}-2^{args.log2n}x{r}B"
-        tr = load_traffic(dom["kernel"], wl)
+        tr = load_traffic(dn, wl)
         roof = {"bound": "hbm", "achieved": dom["GBps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": dom["GBps"] / HBM_PEAK_GBPS if dom["GBps"] else None, "traffic": tr,
-                "kernel": dom["kernel"], "phase": dom["phase"], "avg_launch_ms": dom["ms"],
-                "alg_bytes_per_launch": dom["alg_bytes"]}
+                "frac": dom["GBps"] / HBM_PEAK_GBPS, "traffic": tr,
+                "kernel": dn, "launches_per_step": dom["launches"], "ms_per_step": dom["ms"],
+                "avg_launch_ms": dom["avg_launch_ms"], "alg_bytes_per_launch": dom["alg_bytes_per_launch"]}
     bpr = model_bytes_per_record(n, r)
     t_roof_ms = bpr * n / (HBM_PEAK_GBPS * 1e9) * 1e3
     out = {
@@ -347,6 +395,7 @@ def main():
         "e2e": {"model_bytes_per_record": bpr, "t_roof_ms": t_roof_ms, "frac": t_roof_ms / ms_per_step,
                 "model_GBps": bpr * n / (ms_per_step / 1e3) / 1e9},
         "passes": passes,
+        "kernels": kernels,
         "other_phases_ms": other,
         "step_ms": times,
         "timed_wall_s": wall,
@@ -376,7 +425,7 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_cpu:
         log("timing the CPU oracle on a sample")
-        out["cpu_baseline"] = cpu_baseline(pristine, k, args.cpu_sample_log2)
+        out["cpu_baseline"] = cpu_baseline(pristine, k, args.cpu_sample_log2, args.cpu_single_log2)
     print(json.dumps(out), flush=True)
 
 

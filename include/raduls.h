@@ -220,8 +220,9 @@ int raduls_phase_times(double* host_ms, uint32_t count);
  * single-workgroup kernel, [41] records in tiny buckets, [42] records copied
  * back from tmp, [43] records through one-workgroup radix passes (a record
  * counts once per pass), [44] records finished by wavefront jobs, [45]
- * records finished by workgroup jobs, [46] records finished as tiny buckets.
- * `count` entries are written (47 cover all). */
+ * records finished by workgroup jobs, [46] records finished as tiny buckets,
+ * [47] the largest job finished in registers (0: the workgroup jobs ran in
+ * LDS).  `count` entries are written (48 cover all). */
 int raduls_last_work(uint64_t* host_out, uint32_t count);
 
 /* Bytes of library workspace a sort of n records needs (beyond the caller's

@@ -124,7 +124,9 @@ raduls_tuning default_tuning(uint32_t r, uint32_t k, uint64_t n) {
   t.big_digit_bits = 8;
   t.block_digit_bits = 8;
   uint32_t tile = pow2_floor(std::min<uint64_t>(65536 / r, 256ull * ipt_max(r / 4)));
-  t.tile_records = std::min<uint32_t>(tile, 4096);
+  // tiles stage 64 KiB of records in LDS: 4096 records of 16 bytes, 8192 of
+  // 8 bytes (longer digit runs per tile for small records)
+  t.tile_records = std::min<uint32_t>(tile, 8192);
   t.lds_finish_max = 0;
   t.bitonic_max = 0;
   t.workgroups_per_cu = 2;
@@ -207,13 +209,14 @@ Plan make_plan(uint64_t n, uint32_t r, uint32_t k, const raduls_tuning& t, int c
   p.grid_clear = cus * 4;
   uint64_t W = p.grid_small;
   p.t_big = std::max<uint64_t>(t.big_min, (uint64_t)p.c_fin);
-  // Register finishing (keys of at most 8 bytes, heuristic scheduling): a
-  // 1024-thread workgroup finishes jobs of up to fin_max records, so
-  // buckets up to that size leave the levels.
+  // Register finishing (keys of at most 8 bytes; not while a procedure is
+  // forced or traced, which concern the LDS procedures): a 1024-thread
+  // workgroup finishes jobs of up to fin_max records, so buckets up to that
+  // size leave the levels.
   p.fin_max = 0;
   p.grid_fin = cus;
   const int lds_limit = device_lds_per_block();
-  if (allow_fin && t.reg_finish && k <= 8 && g_sched_mode == RADULS_SCHED_HEURISTIC &&
+  if (allow_fin && t.reg_finish && k <= 8 && g_sched_mode != RADULS_SCHED_FORCED &&
       (lds_limit <= 0 || lds_limit >= (int)(rd::FIN_LDS_BYTES + rd::FIN_STATIC_LDS))) {
     p.fin_max = rd::fin_records_per_thread(p.rw) * rd::FIN_THREADS;
     p.t_big = std::max<uint64_t>(t.big_min, (uint64_t)p.fin_max);
@@ -781,6 +784,7 @@ int raduls_last_work(uint64_t* host_out, uint32_t count) {
   for (auto& b : v) cr += b.count;
   put(2 * rd::LMAX + 2, cr);
   for (uint32_t q = 0; q < 4; q++) put(2 * rd::LMAX + 3 + q, c.stage_records[q]);
+  put(2 * rd::LMAX + 7, p.fin_max);
   return RADULS_OK;
 }
 

@@ -357,15 +357,17 @@ def last_work():
     """Records handled per stage by the last sort.
 
     {'levels': [(in, moved), ...], 'small', 'tiny', 'copy', 'block_pass',
-    'wave_jobs', 'wg_jobs', 'tiny_done'}
+    'wave_jobs', 'wg_jobs', 'tiny_done', 'fin_max'}; 'fin_max' > 0 means the
+    workgroup jobs were finished in registers (k_fin_jobs), else in LDS
+    (k_small_jobs).
     """
-    arr = (_u64 * 47)()
-    _check(lib().raduls_last_work(arr, 47))
+    arr = (_u64 * 48)()
+    _check(lib().raduls_last_work(arr, 48))
     levels = [(arr[2 * l], arr[2 * l + 1]) for l in range(20)]
     while levels and levels[-1] == (0, 0):
         levels.pop()
     return {"levels": levels, "small": arr[40], "tiny": arr[41], "copy": arr[42], "block_pass": arr[43],
-            "wave_jobs": arr[44], "wg_jobs": arr[45], "tiny_done": arr[46]}
+            "wave_jobs": arr[44], "wg_jobs": arr[45], "tiny_done": arr[46], "fin_max": arr[47]}
 
 
 def workspace_bytes(n: int, rec_bytes: int, key_bytes: int) -> int:
