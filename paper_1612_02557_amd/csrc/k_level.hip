@@ -734,25 +734,49 @@ __global__ __launch_bounds__(WG) void k_scatter(Plan p, Work w, uint32_t level, 
   const uint32_t per_wave = p.tile / NWAVES;
   const bool nt = p.nontemporal != 0;
 
-  // The next tile is claimed, and the per-wave counters cleared, just before
-  // a tile's last barrier.
+  constexpr uint32_t RB = 4 * RW;  // record bytes
+  // Tiles are claimed through an atomic ticket.  A tile's records are held in
+  // registers only until they are staged in LDS; the next tile is claimed
+  // before that staging barrier, and its records are loaded into the same
+  // registers while the staged tile is written out.
   auto claim = [&]() {
     uint64_t tk = atomicAdd(&w.ctl->ticket[level], 1u);
     sticket = tk;
     sb = tk < T ? w.tbucket[tk] : 0;
   };
+  Rec<RW> rec[IPT_MAX];
+  // load tile `ticket` of list entry `b` (nothing for a finished claim or a
+  // bucket whose move is skipped); offsets past the bucket read 0
+  auto load_tile = [&](uint64_t ticket, uint32_t b) {
+    if (ticket >= T) return;
+    const Bucket B = list[b];
+    if (B.flags & BF_SKIP) return;
+    const uint64_t r0 = B.begin + (ticket - start[b]) * p.tile;
+    const uint64_t bend = B.begin + B.count;
+    const uint32_t cnt = (uint32_t)min((uint64_t)p.tile, bend - r0);
+    const uint8_t* src = (B.flags & BF_TMP) ? rec1 : rec0;
+    const __amdgpu_buffer_rsrc_t sr = job_rsrc(src + r0 * RB, cnt * RB);
+    const uint32_t voff = (wave * per_wave + lane) * RB;
+#pragma unroll
+    for (uint32_t j = 0; j < IPT_MAX; j++)
+      if (j < IPT) rec[j] = buf_load_rec<RW>(sr, voff, j * 64 * RB);
+  };
   for (uint32_t i = threadIdx.x; i < NWAVES * RMAX; i += WG) wcnt[i] = 0;
   if (threadIdx.x == 0) claim();
   __syncthreads();
+  uint64_t ticket = uniform64(sticket);
+  uint32_t b = uniform32(sb);
+  load_tile(ticket, b);
   for (;;) {
-    const uint64_t ticket = sticket;
-    const uint32_t b = sb;
     if (ticket >= T) break;
     Bucket B = list[b];
     if (B.flags & BF_SKIP) {
       __syncthreads();  // everyone has read the ticket
       if (threadIdx.x == 0) claim();
       __syncthreads();
+      ticket = uniform64(sticket);
+      b = uniform32(sb);
+      load_tile(ticket, b);
       continue;
     }
     uint64_t ti = ticket - start[b];
@@ -766,20 +790,11 @@ __global__ __launch_bounds__(WG) void k_scatter(Plan p, Work w, uint32_t level, 
     uint32_t R = 1u << d;
     uint32_t shift = kf.kbits - B.bit - d;
     uint32_t mask = R - 1u;
-    const uint8_t* src = (B.flags & BF_TMP) ? rec1 : rec0;
     uint8_t* dst = (B.flags & BF_TMP) ? rec0w : rec1w;
 
-    Rec<RW> rec[IPT_MAX];
     uint32_t dg[IPT_MAX];
     uint32_t rk[IPT_MAX];
     uint64_t wbase = r0 + (uint64_t)wave * per_wave;
-#pragma unroll
-    for (uint32_t j = 0; j < IPT_MAX; j++) {
-      if (j < IPT) {
-        uint64_t i = wbase + (uint64_t)j * 64 + lane;
-        if (i < bend) rec[j] = load_rec<RW>(src, i);
-      }
-    }
     RankPart rp[IPT_MAX];
 #pragma unroll
     for (uint32_t j = 0; j < IPT_MAX; j++) {
@@ -823,14 +838,18 @@ __global__ __launch_bounds__(WG) void k_scatter(Plan p, Work w, uint32_t level, 
       const uint64_t* to = w.status + ticket * RS;
       for (uint32_t v = threadIdx.x; v < R; v += WG) gbase[v] = B.begin + to[v] - toff[v];
     }
+    if (threadIdx.x == 0) claim();
     __syncthreads();
+    // the registers are free: the next tile's loads go out now
+    ticket = uniform64(sticket);
+    b = uniform32(sb);
+    load_tile(ticket, b);
     for (uint32_t q = threadIdx.x; q < cnt; q += WG) {
       Rec<RW> r = lds_get<RW>(stage, q);
       uint32_t v = key_digit(rec_key<RW>(r, kf), shift, mask, kf);
       store_rec<RW>(dst, gbase[v] + q, r, nt);
     }
     for (uint32_t i = threadIdx.x; i < NWAVES * RMAX; i += WG) wcnt[i] = 0;
-    if (threadIdx.x == 0) claim();
     __syncthreads();
   }
 }

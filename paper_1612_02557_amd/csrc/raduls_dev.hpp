@@ -125,6 +125,63 @@ __device__ __forceinline__ Rec<RW> lds_get(const uint32_t* s, uint32_t i) {
   return r;
 }
 
+// Buffer access to a range of records: a resource over the range's bytes
+// (wave-uniform base), one VGPR offset per thread and the record slot in the
+// scalar offset, so that holding many records costs no address registers;
+// offsets past the range read 0 and their stores are dropped.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t job_rsrc(const uint8_t* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+template <int RW>
+__device__ __forceinline__ Rec<RW> buf_load_rec(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff) {
+  Rec<RW> r;
+  if constexpr (RW % 4 == 0) {
+#pragma unroll
+    for (int j = 0; j < RW / 4; j++) {
+      const v4u v = __builtin_bit_cast(v4u, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)voff + 16 * j, (int)soff, 0));
+      r.w[4 * j] = v.x; r.w[4 * j + 1] = v.y; r.w[4 * j + 2] = v.z; r.w[4 * j + 3] = v.w;
+    }
+  } else if constexpr (RW % 2 == 0) {
+#pragma unroll
+    for (int j = 0; j < RW / 2; j++) {
+      const v2u v = __builtin_bit_cast(v2u, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)voff + 8 * j, (int)soff, 0));
+      r.w[2 * j] = v.x; r.w[2 * j + 1] = v.y;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < RW; j++) r.w[j] = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)voff + 4 * j, (int)soff, 0);
+  }
+  return r;
+}
+
+template <int RW>
+__device__ __forceinline__ void buf_store_rec(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff, const Rec<RW>& r) {
+  if constexpr (RW % 4 == 0) {
+#pragma unroll
+    for (int j = 0; j < RW / 4; j++) {
+      const v4u v = {r.w[4 * j], r.w[4 * j + 1], r.w[4 * j + 2], r.w[4 * j + 3]};
+      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(__attribute__((ext_vector_type(4))) unsigned int, v), rs,
+                                             (int)voff + 16 * j, (int)soff, 0);
+    }
+  } else if constexpr (RW % 2 == 0) {
+#pragma unroll
+    for (int j = 0; j < RW / 2; j++) {
+      const v2u v = {r.w[2 * j], r.w[2 * j + 1]};
+      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned int, v), rs,
+                                            (int)voff + 8 * j, (int)soff, 0);
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < RW; j++) __builtin_amdgcn_raw_buffer_store_b32(r.w[j], rs, (int)voff + 4 * j, (int)soff, 0);
+  }
+}
+
+__device__ __forceinline__ uint32_t uniform32(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ uint64_t uniform64(uint64_t x) {
+  return (uint64_t)uniform32((uint32_t)x) | ((uint64_t)uniform32((uint32_t)(x >> 32)) << 32);
+}
+
 // ---- keys and digits ------------------------------------------------------
 
 struct KeyFmt {
