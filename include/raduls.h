@@ -174,24 +174,39 @@ int raduls_get_scheduler(int* mode, int* forced_proc);
  * scales (2*F float32) and a uint32 checksum (FNV-1a of everything before
  * it).  Rejected blobs return RADULS_EMODEL and leave the current model. */
 int raduls_load_model(const void* host_blob, size_t bytes);
+/* A bucket whose features, normalized by the blob's means and scales, are
+ * not all within +-RADULS_MLP_OOD_Z lies outside the network's training
+ * range (the scales are the training features' standard deviations): the
+ * heuristic decides it. */
+#define RADULS_MLP_OOD_Z 4.0f
 int raduls_unload_model(void);
 
+/* Set the tuning of all later sorts; NULL returns to the defaults and
+ * forgets the autotuner's results. */
 int raduls_set_tuning(const raduls_tuning* host_tuning);
 int raduls_get_tuning(raduls_tuning* host_tuning);
 int raduls_default_tuning(uint32_t rec_bytes, uint32_t key_bytes, uint64_t n,
                           raduls_tuning* host_tuning);
 /* Autotuner (the paper picked its constants by experiment, Sec. 3.2-3.5).
- * Times candidate tunings -- tile size, finishing-job size, resident
- * workgroups per CU, big-bucket rule, non-temporal stores -- on two probe
- * inputs of min(max(n_hint, 2^16), 2^25) records that it generates on the
- * device (uniform keys; keys with 4096 distinct values; payload = index),
- * the median of three timed sorts each, and makes the candidate with the
- * smallest total the current tuning (raduls_get_tuning reads it).  Results
- * are cached per (rec_bytes, key_bytes, floor(log2 n_hint)), so a second
- * call returns at once.  Allocates and frees 4 * n * rec_bytes bytes of
- * probe buffers (ENOMEM if that fails, the tuning then unchanged) and waits
- * for `stream`.  No tuning changes the bytes a sort produces. */
+ * A coordinate search from the defaults: register finishing on or off,
+ * level digit width (8..11 bits), tile size, finishing-job size, resident
+ * workgroups per CU, big-bucket rule and non-temporal stores, each in turn
+ * taking the value that times best with the others fixed.  Each candidate
+ * is timed on two probe inputs of min(max(n_hint, 2^16), 2^27) records that
+ * it generates on the device (uniform keys; keys with 4096 distinct values;
+ * payload = index), the median of three timed sorts each.  The result is
+ * kept for (rec_bytes, key_bytes, floor(log2 n_hint)) and used by every
+ * later sort of that shape and size class (unless raduls_set_tuning set a
+ * tuning, which takes precedence); a second call for the same class returns
+ * at once.  Allocates and frees 4 * n * rec_bytes bytes of probe buffers
+ * (ENOMEM if that fails, nothing then changed) and waits for `stream`.  No
+ * tuning changes the bytes a sort produces. */
 int raduls_tune(uint32_t rec_bytes, uint32_t key_bytes, uint64_t n_hint, void* stream);
+/* The tuning a sort of n records of this shape would use now (the one set
+ * by raduls_set_tuning, else the autotuner's result for the shape class,
+ * else the defaults). */
+int raduls_effective_tuning(uint32_t rec_bytes, uint32_t key_bytes, uint64_t n,
+                            raduls_tuning* host_tuning);
 
 /* Record one raduls_trace_row per scheduled bucket into `rows` (device,
  * `capacity` rows); every `sample_period`-th eligible bucket (0 = none) is

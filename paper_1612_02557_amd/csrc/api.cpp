@@ -419,8 +419,21 @@ int mark_done(DeviceState& s, hipStream_t stream) {
   return RADULS_OK;
 }
 
+// Autotuner results are kept per record size, key size and size class
+// (floor(log2 n)).
+std::tuple<uint32_t, uint32_t, uint32_t> tuned_key(uint32_t r, uint32_t k, uint64_t n) {
+  const uint64_t hint = std::max<uint64_t>(n, 2);
+  uint32_t cls = 0;
+  while ((2ull << cls) <= hint) cls++;
+  return std::make_tuple(r, k, cls);
+}
+
+// The tuning a sort uses: one set by raduls_set_tuning, else the autotuner's
+// result for its shape class, else the defaults.
 raduls_tuning current_tuning(uint32_t r, uint32_t k, uint64_t n) {
-  return g_has_tuning ? g_tuning : default_tuning(r, k, n);
+  if (g_has_tuning) return g_tuning;
+  auto it = g_tuned.find(tuned_key(r, k, n));
+  return it != g_tuned.end() ? it->second : default_tuning(r, k, n);
 }
 
 // Phase ids for raduls_phase_times: 0 init+seed; for level l: 1+4l prepare
@@ -864,6 +877,7 @@ int raduls_set_tuning(const raduls_tuning* t) {
   if (!t) {
     std::lock_guard<std::mutex> lock(g_mu);
     g_has_tuning = false;
+    g_tuned.clear();
     return RADULS_OK;
   }
   int rc = validate_tuning(*t);
@@ -1027,20 +1041,13 @@ void raduls_release(void) {
 int raduls_tune(uint32_t rec_bytes, uint32_t key_bytes, uint64_t n_hint, void* stream) {
   int rc = check_shape(rec_bytes, key_bytes);
   if (rc) return rc;
-  const uint64_t hint = std::max<uint64_t>(n_hint, 2);
-  uint32_t cls = 0;
-  while ((2ull << cls) <= hint) cls++;
-  const auto key = std::make_tuple(rec_bytes, key_bytes, cls);
+  const auto key = tuned_key(rec_bytes, key_bytes, n_hint);
   {
     std::lock_guard<std::mutex> lock(g_mu);
-    auto it = g_tuned.find(key);
-    if (it != g_tuned.end()) {
-      g_tuning = it->second;
-      g_has_tuning = true;
-      return RADULS_OK;
-    }
+    if (g_tuned.count(key)) return RADULS_OK;
   }
-  const uint64_t n = std::min<uint64_t>(std::max<uint64_t>(hint, 1ull << 16), 1ull << 25);
+  const uint64_t hint = std::max<uint64_t>(n_hint, 2);
+  const uint64_t n = std::min<uint64_t>(std::max<uint64_t>(hint, 1ull << 16), 1ull << 27);
   const size_t bytes = (size_t)n * rec_bytes;
   hipStream_t st = (hipStream_t)stream;
   uint8_t* buf[4] = {nullptr, nullptr, nullptr, nullptr};  // two probes, records, tmp
@@ -1059,26 +1066,9 @@ int raduls_tune(uint32_t rec_bytes, uint32_t key_bytes, uint64_t n_hint, void* s
   HIPCHK(hipEventCreate(&e1));
   const bool had = g_has_tuning;
   const raduls_tuning prev = g_tuning;
-  const raduls_tuning base = default_tuning(rec_bytes, key_bytes, n);
-  std::vector<raduls_tuning> cands;
-  for (uint32_t tile : {base.tile_records, base.tile_records / 2})
-    for (uint32_t job : {0u, 1024u})
-      for (uint32_t wpc : {2u, 1u})
-        for (uint32_t nt : {0u, 1u})
-          for (uint32_t rule : {0u, 1u}) {
-            raduls_tuning t = base;
-            t.tile_records = tile;
-            t.big_min = 2ull * tile;
-            t.job_records = job;
-            t.workgroups_per_cu = wpc;
-            t.nontemporal = nt;
-            t.big_rule = rule;
-            if (validate_tuning(t) == RADULS_OK) cands.push_back(t);
-          }
-  double best_ms = 1e300;
-  raduls_tuning best = base;
   int err = RADULS_OK;
-  for (const raduls_tuning& t : cands) {
+  // median of three timed sorts (after one untimed) of each probe, summed
+  auto measure = [&](const raduls_tuning& t) -> double {
     {
       std::lock_guard<std::mutex> lock(g_mu);
       g_tuning = t;
@@ -1086,7 +1076,7 @@ int raduls_tune(uint32_t rec_bytes, uint32_t key_bytes, uint64_t n_hint, void* s
     }
     double total = 0.0;
     for (int probe = 0; probe < 2 && err == RADULS_OK; probe++) {
-      float ms[4];
+      float ms[4] = {0, 0, 0, 0};
       for (int rep = 0; rep < 4 && err == RADULS_OK; rep++) {
         if (hipMemcpyAsync(buf[2], buf[probe], bytes, hipMemcpyDeviceToDevice, st) != hipSuccess) { err = RADULS_EHIP; break; }
         (void)hipEventRecord(e0, st);
@@ -1095,24 +1085,51 @@ int raduls_tune(uint32_t rec_bytes, uint32_t key_bytes, uint64_t n_hint, void* s
         if (hipEventSynchronize(e1) != hipSuccess) err = RADULS_EHIP;
         (void)hipEventElapsedTime(&ms[rep], e0, e1);
       }
-      std::sort(ms + 1, ms + 4);  // the first run warms the workspace up
+      std::sort(ms + 1, ms + 4);
       total += ms[2];
     }
-    if (err != RADULS_OK) break;
-    if (total < best_ms) { best_ms = total; best = t; }
-  }
+    return total;
+  };
+  // Coordinate search from the defaults: each parameter in turn takes the
+  // value that times best with the others at their best so far.
+  raduls_tuning best = default_tuning(rec_bytes, key_bytes, n);
+  double best_ms = measure(best);
+  auto try_values = [&](auto set, std::initializer_list<uint32_t> values) {
+    for (uint32_t v : values) {
+      if (err != RADULS_OK) return;
+      raduls_tuning t = best;
+      set(t, v);
+      if (validate_tuning(t) != RADULS_OK || check_levels(key_bytes, t) != RADULS_OK) continue;
+      if (memcmp(&t, &best, sizeof(t)) == 0) continue;
+      const double ms = measure(t);
+      if (err == RADULS_OK && ms < best_ms) { best_ms = ms; best = t; }
+    }
+  };
+  const uint32_t tile0 = best.tile_records;
+  try_values([](raduls_tuning& t, uint32_t v) { t.reg_finish = v; }, {1u, 0u});
+  try_values([](raduls_tuning& t, uint32_t v) { t.big_digit_bits = v; }, {8u, 9u, 10u, 11u});
+  try_values([](raduls_tuning& t, uint32_t v) { t.tile_records = v; t.big_min = 2ull * v; }, {tile0, tile0 / 2});
+  try_values([](raduls_tuning& t, uint32_t v) { t.job_records = v; }, {0u, 1024u, 4096u});
+  try_values([](raduls_tuning& t, uint32_t v) { t.workgroups_per_cu = v; }, {2u, 1u});
+  try_values([](raduls_tuning& t, uint32_t v) { t.big_rule = v; }, {1u, 0u});
+  try_values([](raduls_tuning& t, uint32_t v) { t.nontemporal = v; }, {0u, 1u});
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   for (auto& f : buf) hipFree(f);
   std::lock_guard<std::mutex> lock(g_mu);
-  if (err != RADULS_OK) {
-    g_tuning = prev;
-    g_has_tuning = had;
-    return err == RADULS_EHIP ? fail(RADULS_EHIP, "autotuner run failed") : err;
-  }
+  g_tuning = prev;
+  g_has_tuning = had;
+  if (err != RADULS_OK) return err == RADULS_EHIP ? fail(RADULS_EHIP, "autotuner run failed") : err;
   g_tuned[key] = best;
-  g_tuning = best;
-  g_has_tuning = true;
+  return RADULS_OK;
+}
+
+int raduls_effective_tuning(uint32_t rec_bytes, uint32_t key_bytes, uint64_t n, raduls_tuning* t) {
+  if (!t) return fail(RADULS_EINVAL, "null pointer");
+  int rc = check_shape(rec_bytes, key_bytes);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lock(g_mu);
+  *t = current_tuning(rec_bytes, key_bytes, n);
   return RADULS_OK;
 }
 

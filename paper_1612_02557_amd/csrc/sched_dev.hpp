@@ -3,8 +3,9 @@
 // The heuristic restates the paper's thresholds (Sec. 3.2-3.5) over the GPU
 // procedures; the learned mode evaluates a small network (one thread per
 // bucket) that predicts each procedure's log-time and takes the cheapest
-// feasible one, falling back to the heuristic on a missing model or a
-// non-finite prediction.
+// feasible one, falling back to the heuristic on a missing model, a
+// non-finite prediction, or a bucket outside the network's training range
+// (a normalized feature beyond RADULS_MLP_OOD_Z).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -79,8 +80,13 @@ __device__ __forceinline__ uint32_t mlp_choose(const float* __restrict__ model, 
   const float* mean = model + MLP_NPARAM;
   const float* scale = mean + MLP_F;
   float x[MLP_F];
+  bool ood = false;
 #pragma unroll
-  for (uint32_t i = 0; i < MLP_F; i++) x[i] = (feat[i] - mean[i]) / scale[i];
+  for (uint32_t i = 0; i < MLP_F; i++) {
+    x[i] = (feat[i] - mean[i]) / scale[i];
+    ood = ood || !(fabsf(x[i]) <= RADULS_MLP_OOD_Z);
+  }
+  if (ood) return 0xFFFFFFFFu;  // outside the training range: the heuristic decides
   float h1[MLP_H];
 #pragma unroll 4
   for (uint32_t j = 0; j < MLP_H; j++) {
@@ -131,8 +137,13 @@ __device__ __forceinline__ uint32_t mlp_choose_wave(const float* __restrict__ mo
   const uint32_t j = __lane_id() & (MLP_H - 1);
   const bool own = __lane_id() < MLP_H;
   float x[MLP_F];
+  bool ood = false;
 #pragma unroll
-  for (uint32_t i = 0; i < MLP_F; i++) x[i] = (feat[i] - mean[i]) / scale[i];
+  for (uint32_t i = 0; i < MLP_F; i++) {
+    x[i] = (feat[i] - mean[i]) / scale[i];
+    ood = ood || !(fabsf(x[i]) <= RADULS_MLP_OOD_Z);
+  }
+  if (ood) return 0xFFFFFFFFu;  // the same in every lane
   float a = b1[j];
 #pragma unroll
   for (uint32_t i = 0; i < MLP_F; i++) a = fmaf(W1[j * MLP_F + i], x[i], a);

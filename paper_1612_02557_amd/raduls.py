@@ -84,6 +84,7 @@ _SIGS = {
     "raduls_set_tuning": (_i32, [ctypes.POINTER(Tuning)]),
     "raduls_get_tuning": (_i32, [ctypes.POINTER(Tuning)]),
     "raduls_default_tuning": (_i32, [_u32, _u32, _u64, ctypes.POINTER(Tuning)]),
+    "raduls_effective_tuning": (_i32, [_u32, _u32, _u64, ctypes.POINTER(Tuning)]),
     "raduls_set_trace": (_i32, [_vp, _u64, _u32]),
     "raduls_trace_count": (_i32, [ctypes.POINTER(_u64), _vp]),
     "raduls_get_stats": (_i32, [ctypes.POINTER(Stats)]),
@@ -299,9 +300,17 @@ def set_tuning(t: Tuning | None):
 
 
 def tune(rec_bytes: int, key_bytes: int, n_hint: int, stream=None) -> Tuning:
-    """Run the library's autotuner; returns the tuning it made current."""
+    """Run the library's autotuner for this shape and size class; returns the
+    tuning later sorts of that shape and size class use."""
     _check(lib().raduls_tune(rec_bytes, key_bytes, n_hint, _stream(stream)))
-    return get_tuning()
+    return effective_tuning(rec_bytes, key_bytes, n_hint)
+
+
+def effective_tuning(rec_bytes: int, key_bytes: int, n: int) -> Tuning:
+    """The tuning a sort of n records of this shape would use now."""
+    t = Tuning()
+    _check(lib().raduls_effective_tuning(rec_bytes, key_bytes, n, ctypes.byref(t)))
+    return t
 
 
 def get_tuning() -> Tuning | None:

@@ -301,7 +301,21 @@ def biased_model(prefer: int, seed: int = 0):
     b3 = theta[-P:]
     b3[:] = 5.0
     b3[prefer] = -5.0
-    return theta, np.zeros(F), np.ones(F)
+    # scales wide enough that every bucket is inside the training range
+    return theta, np.zeros(F), np.full(F, 100.0)
+
+
+OOD_Z = 4.0   # RADULS_MLP_OOD_Z
+
+
+def heuristic_choice(row):
+    """The paper's rule restricted to the feasible set of a counterfactual row."""
+    m, feas = int(row["count"]), int(row["observed"])
+    tiny = sched_ref.TINY_NARROW if row["features"][8] > 0.5 else sched_ref.TINY
+    for q, ok in ((sched_ref.PROC_BITONIC, m < tiny), (sched_ref.PROC_RADIX, True), (sched_ref.PROC_LSD, True)):
+        if ok and (feas >> q) & 1:
+            return q
+    return sched_ref.PROC_BITONIC
 
 
 @pytest.mark.parametrize("dist", ["uniform", "zipf", "mix"])
@@ -372,7 +386,7 @@ def test_learned_choice_matches_host_network(R):
     rng = np.random.default_rng(4)
     theta = rng.normal(0.0, 0.2, mlp_ref.n_params(F, H, P))
     theta[-P:] = [0.0, 1.5, -1.5]            # well separated outputs
-    mean, scale = rng.normal(0, 0.5, F), rng.uniform(1.0, 3.0, F)
+    mean, scale = rng.normal(0, 0.5, F), rng.uniform(3.0, 6.0, F)
     R.load_model(R.model_blob(theta, mean, scale))
     R.set_scheduler(R.SCHED_LEARNED)
     try:
@@ -386,7 +400,14 @@ def test_learned_choice_matches_host_network(R):
     assert len(cf) > 0
     x = (cf["features"].astype(np.float32) - mean.astype(np.float32)) / scale.astype(np.float32)
     y = mlp_ref.forward_f32(theta, x, F, H, P)
-    for row, yy in zip(cf, y):
+    z = np.abs(x).max(axis=1)
+    assert (z < OOD_Z - 1e-3).sum() > 0 and (z > OOD_Z + 1e-3).sum() > 0, "both sides of the range"
+    for row, yy, zz in zip(cf, y, z):
+        if abs(zz - OOD_Z) < 1e-3:
+            continue                          # on the edge of the training range
+        if zz > OOD_Z:
+            assert int(row["chosen"]) == heuristic_choice(row), "outside the range: the heuristic decides"
+            continue
         feas = int(row["observed"])
         cand = [q for q in range(P) if (feas >> q) & 1]
         best = min(cand, key=lambda q: (yy[q], q))
@@ -394,6 +415,27 @@ def test_learned_choice_matches_host_network(R):
         if len(srt) > 1 and srt[1] - srt[0] < 1e-3:
             continue                          # too close to call across evaluation orders
         assert int(row["chosen"]) == best
+
+
+def test_learned_out_of_range_falls_back(R):
+    """A network whose training range (means and scales) excludes every
+    bucket is never consulted: the choices are the heuristic's."""
+    note("learned scheduler, buckets outside the training range")
+    theta, _, _ = biased_model(sched_ref.PROC_LSD)
+    mean = np.full(F, 1000.0)                 # z = (f - 1000) / 1 for features of order 1..30
+    R.load_model(R.model_blob(theta, mean, np.ones(F)))
+    R.set_scheduler(R.SCHED_LEARNED)
+    try:
+        host = synth.generate(synth.Spec(n=2_000_000, dist="mix", seed=26))
+        got, tr = traced_sort(R, host, 8, period=1)
+    finally:
+        R.set_scheduler(R.SCHED_HEURISTIC)
+        R.unload_model()
+    assert np.array_equal(got, oracle.sort(host, 8))
+    cf = tr[(tr["flags"] & 1) != 0]
+    assert len(cf) > 0
+    for row in cf[:5000]:
+        assert int(row["chosen"]) == heuristic_choice(row)
 
 
 def test_counterfactual_rows(R):
@@ -440,6 +482,7 @@ def test_model_blob_validation(R):
 def test_autotuner_picks_a_valid_tuning(R):
     import time
     note("autotuner r=16 k=8 n_hint=2^22")
+    R.set_tuning(None)
     t0 = time.perf_counter()
     t = R.tune(16, 8, 1 << 22)
     first = time.perf_counter() - t0
@@ -447,14 +490,20 @@ def test_autotuner_picks_a_valid_tuning(R):
         assert t is not None
         d = t.as_dict()
         assert d["tile_records"] in (2048, 4096) and d["workgroups_per_cu"] in (1, 2)
+        assert 8 <= d["big_digit_bits"] <= 11 and d["reg_finish"] in (0, 1)
         t0 = time.perf_counter()
         assert R.tune(16, 8, (1 << 22) + 5).as_dict() == d     # same size class: cached
         assert time.perf_counter() - t0 < first
+        # the result applies to its shape and size class only
+        assert R.effective_tuning(16, 8, (1 << 23) - 1).as_dict() == d
+        assert R.effective_tuning(16, 8, 1 << 20).as_dict() == R.default_tuning(16, 8, 1 << 20).as_dict()
+        assert R.effective_tuning(8, 8, 1 << 22).as_dict() == R.default_tuning(8, 8, 1 << 22).as_dict()
         for dist in ("uniform", "zipf"):
-            host = synth.generate(synth.Spec(n=1 << 21, dist=dist, seed=31))
+            host = synth.generate(synth.Spec(n=(1 << 22) + 12345, dist=dist, seed=31))
             dev = to_dev(host)
             R.sort(dev, 8)
             R.sync_check()
             assert np.array_equal(dev.cpu().numpy(), oracle.sort(host, 8)), dist
     finally:
         R.set_tuning(None)
+    assert R.effective_tuning(16, 8, 1 << 22).as_dict() == R.default_tuning(16, 8, 1 << 22).as_dict()
