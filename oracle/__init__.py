@@ -6,7 +6,8 @@ path (``paper_1612_02557_amd``) never does, and shares no code with it.
 
 * ``oracle_sort.c`` (C, built into ``liboracle.so``): stable LSD byte-wise
   counting sort (paper, Sec. 1), its T-thread form, one-digit histogram and
-  one-digit stable partition.
+  one-digit stable partition, and duplicate removal with run counts over
+  key-ordered records (the k-mer counting application, Sec. 5).
 * ``mlp_ref`` (numpy, float64): the scheduler network's forward pass, loss,
   gradients and Adam step.
 * ``sched_ref`` (Python): the heuristic procedure rules restated from the
@@ -19,4 +20,6 @@ from .sort_ref import (  # noqa: F401
     sort_segments,
     partition,
     digit_histogram,
+    count_runs,
+    sort_count,
 )

@@ -209,3 +209,30 @@ int oracle_sort_segments(uint8_t* rec, const uint64_t* off, uint32_t S, uint32_t
   }
   return 0;
 }
+
+/*
+ * oracle_count_runs: duplicate removal with counting over records already in
+ * key order -- the second half of the k-mer counting application of Sec. 5,
+ * where the k-mers of a bin are sorted and then their duplicates removed.
+ * A run is a maximal stretch of consecutive records whose keys (bytes
+ * [0, k)) are identical.  For the j-th run, uniq receives its first record
+ * (all r bytes; with a stable sort that is the earliest input record of that
+ * key) and counts[j] its length.  *u receives the number of runs.  uniq and
+ * counts must hold n entries.  Returns 0, or -1 on inconsistent arguments.
+ */
+int oracle_count_runs(const uint8_t* sorted, uint64_t n, uint32_t r, uint32_t k,
+                      uint8_t* uniq, uint64_t* counts, uint64_t* u) {
+  if (k == 0 || k > r) return -1;
+  uint64_t runs = 0;
+  for (uint64_t i = 0; i < n; i++) {
+    const uint8_t* x = sorted + i * r;
+    if (i == 0 || memcmp(x, x - r, k) != 0) {  /* a new key starts a run */
+      memcpy(uniq + runs * r, x, r);
+      counts[runs] = 0;
+      runs += 1;
+    }
+    counts[runs - 1] += 1;
+  }
+  *u = runs;
+  return 0;
+}

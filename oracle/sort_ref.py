@@ -28,8 +28,10 @@ def lib():
                                        ctypes.c_uint32, ctypes.c_uint32]
         L.oracle_sort_segments.argtypes = [_u8p, _u64p, ctypes.c_uint32, ctypes.c_uint32,
                                            ctypes.c_uint32]
+        L.oracle_count_runs.argtypes = [_u8p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, _u8p, _u64p,
+                                        _u64p]
         for f in (L.oracle_sort, L.oracle_sort_threads, L.oracle_digit_histogram,
-                  L.oracle_partition, L.oracle_sort_segments):
+                  L.oracle_partition, L.oracle_sort_segments, L.oracle_count_runs):
             f.restype = ctypes.c_int
         _LIB = L
     return _LIB
@@ -99,3 +101,23 @@ def digit_histogram(rec: np.ndarray, key_bytes: int, shift: int, bits: int) -> n
                                     cnt.ctypes.data_as(_u64p)) != 0:
         raise ValueError("oracle_digit_histogram rejected the arguments")
     return cnt
+
+
+def count_runs(sorted_rec: np.ndarray, key_bytes: int):
+    """Runs of equal keys in key-ordered records: (first record of each run,
+    run lengths as uint64), both in key order."""
+    src = _as_records(sorted_rec)
+    n, r = src.shape
+    uniq = np.empty_like(src)
+    counts = np.empty(n, dtype=np.uint64)
+    u = np.zeros(1, dtype=np.uint64)
+    if lib().oracle_count_runs(_p(src), n, r, key_bytes, _p(uniq), counts.ctypes.data_as(_u64p),
+                               u.ctypes.data_as(_u64p)) != 0:
+        raise ValueError("oracle_count_runs rejected the arguments")
+    m = int(u[0])
+    return uniq[:m].copy(), counts[:m].copy()
+
+
+def sort_count(rec: np.ndarray, key_bytes: int):
+    """Stable sort, then duplicate removal with counts (k-mer counting, Sec. 5)."""
+    return count_runs(sort(rec, key_bytes), key_bytes)

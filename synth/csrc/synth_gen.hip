@@ -16,6 +16,8 @@ struct Bases {
   uint64_t key, key_hi, zipf, mix, salt_lo, salt_hi;
   uint64_t payload[16];
   uint64_t p24;
+  uint64_t genome, kmerpos, kmererr;  // k-mer keys: stream bases
+  uint64_t windows, bases;            // start positions W, bases per k-mer K
 };
 
 __device__ __forceinline__ uint64_t mix64(uint64_t z) {
@@ -31,7 +33,7 @@ __global__ void k_fill(uint32_t* out, uint64_t i0, uint64_t count, uint32_t r, u
   if (t >= count) return;
   uint64_t i = i0 + t;
   uint64_t lo = val(B.key, i), hi = val(B.key_hi, i);
-  int code = dist;  // 0 uniform, 1 zipf, 2 prefix, 3 mix
+  int code = dist;  // 0 uniform, 1 zipf, 2 prefix, 3 mix, 4 k-mers
   if (dist == 3) {
     uint64_t c = val(B.mix, i) >> 11;
     code = c < MIX_T_UNIFORM ? 0 : (c < MIX_T_ZIPF ? 1 : 2);
@@ -46,6 +48,26 @@ __global__ void k_fill(uint32_t* out, uint64_t i0, uint64_t count, uint32_t r, u
     uint64_t j = (uint64_t)(a < m ? a : m - 1) + 1;
     lo = mix64(j ^ B.salt_lo);
     hi = mix64(j ^ B.salt_hi);
+  } else if (code == 4) {
+    // bits [2p, 2p + 2K) of the genome, 32 bases per stream word
+    const uint64_t K = B.bases;
+    const uint64_t b = 2 * (val(B.kmerpos, i) % B.windows);
+    const uint64_t w0 = b >> 6, s = b & 63;
+    const uint64_t g0 = val(B.genome, w0), g1 = val(B.genome, w0 + 1), g2 = val(B.genome, w0 + 2);
+    lo = s ? (g0 >> s) | (g1 << (64 - s)) : g0;
+    hi = s ? (g1 >> s) | (g2 << (64 - s)) : g1;
+    if (2 * K <= 64) {
+      hi = 0;
+      if (2 * K < 64) lo &= (1ull << (2 * K)) - 1;
+    } else if (2 * K < 128) {
+      hi &= (1ull << (2 * K - 64)) - 1;
+    }
+    const uint64_t e = val(B.kmererr, i);
+    if ((e >> 58) == 0) {  // one substituted base
+      const uint64_t q = (e & 0xFFFF) % K;
+      const uint64_t flip = ((e >> 16) % 3 + 1) << ((2 * q) & 63);
+      if (q < 32) lo ^= flip; else hi ^= flip;
+    }
   } else if (code == 2) {
     const uint64_t mask40 = (1ull << 40) - 1;
     if (k == 8) lo = (B.p24 << 40) | (lo & mask40);
@@ -78,6 +100,9 @@ extern "C" int synth_fill(void* out, uint64_t i0, uint64_t count, uint32_t rec_b
   B.salt_lo = bases[4]; B.salt_hi = bases[5];
   for (int w = 0; w < 16; w++) B.payload[w] = bases[6 + w];
   B.p24 = bases[22];
+  B.genome = bases[23]; B.kmerpos = bases[24]; B.kmererr = bases[25];
+  B.windows = bases[26]; B.bases = bases[27];
+  if (dist == 4 && (B.windows == 0 || B.bases == 0 || B.bases > 4ull * key_bytes)) return -1;
   (void)hipGetLastError();  // report this call's launches only
   // a launch covers fewer than 2^32 work-items: fill 2^30 records per launch
   const uint64_t step = 1ull << 30;

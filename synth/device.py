@@ -43,13 +43,16 @@ def lib():
     return _lib
 
 
-def _bases(seed: int) -> np.ndarray:
+def _bases(spec: gen.Spec) -> np.ndarray:
+    seed = spec.seed
     S = gen.STREAMS
     b = [gen.stream_base(seed, S["KEY"]), gen.stream_base(seed, S["KEY_HI"]), gen.stream_base(seed, S["ZIPF"]),
          gen.stream_base(seed, S["MIX"]), gen.stream_base(seed, S["ZIPF_SALT_LO"]),
          gen.stream_base(seed, S["ZIPF_SALT_HI"])]
     b += [gen.stream_base(seed, S["PAYLOAD"] + w) for w in range(16)]
     b += [gen.stream_base(seed, S["PREFIX"]) >> 40]
+    b += [gen.stream_base(seed, S["GENOME"]), gen.stream_base(seed, S["KMERPOS"]), gen.stream_base(seed, S["KMERERR"])]
+    b += [spec.windows, spec.bases]
     return np.array(b, dtype=np.uint64)
 
 
@@ -65,9 +68,9 @@ def fill(out, spec: gen.Spec, i0: int = 0, dist: str | None = None, stream=None)
     """Write records i0 .. i0+len(out)-1 of ``spec`` into ``out`` (CUDA uint8 [m, rec_bytes])."""
     import torch
     d = dist or spec.dist
-    code = {"uniform": 0, "bytes": 0, "zipf": 1, "prefix": 2, "mix": 3}[d]
+    code = gen.DIST_CODE[d]
     cdf = _cdf(spec.zipf_s, spec.zipf_m, out.device)
-    bases = _bases(spec.seed)
+    bases = _bases(spec)
     st = torch.cuda.current_stream().cuda_stream if stream is None else stream
     rc = lib().synth_fill(out.data_ptr(), i0, out.shape[0], spec.rec_bytes, spec.key_bytes, code,
                           1 if spec.payload == "index" else 0, bases.ctypes.data, cdf.data_ptr(), spec.zipf_m, st)

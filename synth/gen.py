@@ -19,6 +19,17 @@ Record bytes for record i (key_bytes = k, rec_bytes = r):
       mix     : per record, from stream MIX: uniform with probability 1/2,
                 zipf with 3/10, prefix with 1/5
       bytes   : same as uniform (every key byte random); any k
+      kmer    : k-mers of reads drawn from one synthetic genome (the data of
+                the k-mer counting application, paper Sec. 4-5): a genome of
+                W + K - 1 bases, two bits each, 32 bases per word of stream
+                GENOME; W = max(n // kmer_cov, 1) start positions; record i
+                takes the K bases at position p = (stream KMERPOS) mod W,
+                i.e. bits [2p, 2p + 2K) of the genome, and with probability
+                1/64 (top 6 bits of stream KMERERR zero) one base
+                substituted: base (e & 0xFFFF) mod K XOR ((e >> 16) mod 3 + 1)
+                (a sequencing error).  Every genome position is drawn about
+                kmer_cov times, so most keys repeat.  K = kmer_len, at most
+                4 * key_bytes
   * payload = bytes [k, r):
       index   : the first 8 payload bytes hold i as a little-endian uint64
                 (truncated if fewer), later bytes random
@@ -46,6 +57,9 @@ STREAMS = {
     "ZIPF_SALT_LO": 12,
     "ZIPF_SALT_HI": 13,
     "PREFIX": 14,
+    "GENOME": 15,
+    "KMERPOS": 16,
+    "KMERERR": 17,
     "PAYLOAD": 32,  # 32, 33, ... one stream per 8 payload bytes
 }
 
@@ -53,8 +67,8 @@ STREAMS = {
 MIX_T_UNIFORM = 1 << 52                 # 1/2 of 2**53
 MIX_T_ZIPF = 7205759403792793           # floor(0.8 * 2**53)
 
-DISTS = ("uniform", "zipf", "prefix", "mix", "bytes")
-DIST_CODE = {"uniform": 0, "zipf": 1, "prefix": 2, "mix": 3, "bytes": 0}
+DISTS = ("uniform", "zipf", "prefix", "mix", "bytes", "kmer")
+DIST_CODE = {"uniform": 0, "zipf": 1, "prefix": 2, "mix": 3, "bytes": 0, "kmer": 4}
 
 
 def _mix64_np(z: np.ndarray) -> np.ndarray:
@@ -118,6 +132,8 @@ class Spec:
     seed: int = 1
     zipf_s: float = 1.1
     zipf_m: int = 1 << 20
+    kmer_len: int = 0        # bases per k-mer (0: 4 * key_bytes)
+    kmer_cov: int = 16       # records per genome position, on average
 
     def __post_init__(self):
         if self.dist not in DISTS:
@@ -130,6 +146,16 @@ class Spec:
             raise ValueError("prefix keys need key_bytes 8 or 16")
         if self.rec_bytes % 4 or self.rec_bytes > 64:
             raise ValueError("rec_bytes must be a multiple of 4, at most 64")
+        if self.dist == "kmer" and not (1 <= self.bases <= 4 * self.key_bytes and self.kmer_cov >= 1):
+            raise ValueError("kmer keys need 1 <= kmer_len <= 4 * key_bytes and kmer_cov >= 1")
+
+    @property
+    def bases(self) -> int:
+        return self.kmer_len or 4 * self.key_bytes
+
+    @property
+    def windows(self) -> int:
+        return max(self.n // self.kmer_cov, 1)
 
 
 def _key_words(spec: Spec, i0: int, i1: int, dist_code: np.ndarray | None = None):
@@ -140,6 +166,8 @@ def _key_words(spec: Spec, i0: int, i1: int, dist_code: np.ndarray | None = None
     d = spec.dist
     if d in ("uniform", "bytes"):
         return lo, hi
+    if d == "kmer":
+        return _kmer_words(spec, i0, i1)
     if d == "mix":
         c = uniform_u64(seed, STREAMS["MIX"], i0, i1) >> np.uint64(11)
         code = np.where(c < np.uint64(MIX_T_UNIFORM), 0,
@@ -165,6 +193,45 @@ def _key_words(spec: Spec, i0: int, i1: int, dist_code: np.ndarray | None = None
             lo[ps] = (p24 << np.uint64(40)) | (lo[ps] & mask40)
         else:
             hi[ps] = (p24 << np.uint64(40)) | (hi[ps] & mask40)
+    return lo, hi
+
+
+def _stream_at(seed: int, stream: int, idx: np.ndarray) -> np.ndarray:
+    """Values of a stream at arbitrary indices (uint64 array)."""
+    base = np.uint64(stream_base(seed, stream))
+    with np.errstate(over="ignore"):
+        state = base + (idx.astype(np.uint64) + np.uint64(1)) * np.uint64(GAMMA)
+    return _mix64_np(state)
+
+
+def _kmer_words(spec: Spec, i0: int, i1: int):
+    seed, K = spec.seed, spec.bases
+    p = uniform_u64(seed, STREAMS["KMERPOS"], i0, i1) % np.uint64(spec.windows)
+    b = p * np.uint64(2)
+    w0 = b >> np.uint64(6)
+    s = b & np.uint64(63)
+    g0 = _stream_at(seed, STREAMS["GENOME"], w0)
+    g1 = _stream_at(seed, STREAMS["GENOME"], w0 + np.uint64(1))
+    g2 = _stream_at(seed, STREAMS["GENOME"], w0 + np.uint64(2))
+    z = s == 0
+    inv = np.where(z, np.uint64(1), np.uint64(64) - s)   # any shift where s == 0
+    lo = np.where(z, g0, (g0 >> s) | (g1 << inv))
+    hi = np.where(z, g1, (g1 >> s) | (g2 << inv))
+    if 2 * K <= 64:
+        hi = np.zeros_like(hi)
+        if 2 * K < 64:
+            lo &= np.uint64((1 << (2 * K)) - 1)
+    elif 2 * K < 128:
+        hi &= np.uint64((1 << (2 * K - 64)) - 1)
+    e = uniform_u64(seed, STREAMS["KMERERR"], i0, i1)
+    err = (e >> np.uint64(58)) == 0
+    q = (e & np.uint64(0xFFFF)) % np.uint64(K)
+    flip = ((e >> np.uint64(16)) % np.uint64(3)) + np.uint64(1)
+    sh = (np.uint64(2) * q) & np.uint64(63)
+    in_lo = err & (q < 32)
+    in_hi = err & (q >= 32)
+    lo = np.where(in_lo, lo ^ (flip << sh), lo)
+    hi = np.where(in_hi, hi ^ (flip << sh), hi)
     return lo, hi
 
 

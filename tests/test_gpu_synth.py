@@ -32,6 +32,21 @@ def test_device_generator_matches_host(dist, r, k, payload):
     assert np.array_equal(got, want), f"first differing record {int(np.argmax((got != want).any(axis=1)))}"
 
 
+@pytest.mark.parametrize("r,k,bases", [(8, 8, 21), (8, 8, 32), (16, 8, 31), (16, 16, 40), (16, 16, 64),
+                                      (32, 16, 55), (4, 4, 3)])
+def test_device_kmers_match_host(r, k, bases):
+    import torch
+    from synth import device
+    n, i0 = 5003, 77777
+    note(f"synth kmer r={r} k={k} K={bases} i0={i0}")
+    spec = synth.Spec(n=i0 + n, rec_bytes=r, key_bytes=k, dist="kmer", kmer_len=bases, payload="random", seed=9)
+    want = synth.generate(spec, i0, i0 + n)
+    out = torch.empty((n, r), dtype=torch.uint8, device="cuda")
+    device.fill(out, spec, i0=i0)
+    got = out.cpu().numpy()
+    assert np.array_equal(got, want), f"first differing record {int(np.argmax((got != want).any(axis=1)))}"
+
+
 def test_device_segments_match_host():
     import torch
     from synth import device

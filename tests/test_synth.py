@@ -15,7 +15,7 @@ def test_splitmix64_published_vectors():
     assert synth.splitmix64(3 * g) == 0x06C45D188009454F
 
 
-@pytest.mark.parametrize("dist", ["uniform", "zipf", "prefix", "mix", "bytes"])
+@pytest.mark.parametrize("dist", ["uniform", "zipf", "prefix", "mix", "bytes", "kmer"])
 def test_chunks_reproduce_slices(dist):
     k = 8 if dist != "bytes" else 5
     sp = synth.Spec(n=5000, rec_bytes=32, key_bytes=k, dist=dist, payload="random", seed=9)
@@ -67,3 +67,34 @@ def test_segment_sizes_log_uniform():
     assert abs(np.log2(np.median(s)) - 16) < 0.2
     off = synth.segment_offsets(s)
     assert off[0] == 0 and off[-1] == s.sum()
+
+
+@pytest.mark.parametrize("k,bases", [(8, 21), (8, 32), (16, 40), (16, 64)])
+def test_kmers_are_genome_substrings(k, bases):
+    """Error-free k-mer keys are K consecutive bases of one genome, read here
+    base by base from Python integers (not the generator's word shifts);
+    about 1/64 of the records carry exactly one substituted base."""
+    n = 4000
+    sp = synth.Spec(n=n, rec_bytes=16, key_bytes=k, dist="kmer", kmer_len=bases, kmer_cov=4, seed=5)
+    rec = synth.generate(sp)
+    S = synth.STREAMS
+    pos = synth.uniform_u64(5, S["KMERPOS"], 0, n) % np.uint64(sp.windows)
+    words = synth.uniform_u64(5, S["GENOME"], 0, (sp.windows + bases) // 32 + 2)
+    genome = [int(w) for w in words]
+
+    def base(q):
+        return (genome[q // 32] >> (2 * (q % 32))) & 3
+
+    errors = 0
+    for i in range(n):
+        key = int.from_bytes(bytes(rec[i, :k]), "little")
+        want = sum(base(int(pos[i]) + j) << (2 * j) for j in range(bases))
+        diff = key ^ want
+        if diff:
+            errors += 1
+            j = (diff.bit_length() - 1) // 2
+            assert diff >> (2 * j) in (1, 2, 3) and diff & ((1 << (2 * j)) - 1) == 0, "one base differs"
+            assert j < bases
+    assert abs(errors / n - 1 / 64) < 0.01
+    # every start position is drawn about kmer_cov times
+    assert abs(n / len(np.unique(pos)) - 4 / (1 - math.exp(-4))) < 0.3
