@@ -159,6 +159,31 @@ int raduls_sort_segmented(void* records, void* tmp, const uint64_t* seg_offsets,
 int raduls_partition(const void* in, void* out, uint64_t n, uint32_t rec_bytes, uint32_t key_bytes,
                      uint32_t shift, uint32_t bits, uint64_t* counts, void* stream);
 
+/* Duplicate removal with counts over records in key order (paper, Sec. 5:
+ * a k-mer counter sorts the k-mers of a bin and removes the duplicates).
+ * A run is a maximal stretch of consecutive records of `sorted` (device, n
+ * records) with identical keys.  For the j-th run (in record order)
+ * uniq[j] (device, room for n records) receives its first record, all
+ * rec_bytes bytes, and counts[j] (device, room for n uint64) its length;
+ * *num_runs (device uint64) receives the number of runs U.  Entries at U and
+ * beyond are left as they were.  uniq may be `sorted` itself (the runs are
+ * then compacted in place) or must not overlap it; counts and num_runs
+ * overlap nothing.  Buffers of records are 16-byte aligned, counts and
+ * num_runs 8-byte aligned.  One pass over the records (a decoupled
+ * look-back over tiles); stream-ordered, nothing is allocated after the
+ * first call of a size.  A look-back wait that gives up is reported by
+ * raduls_sync_check() (RADULS_EDEVICE); the outputs are then incomplete. */
+int raduls_count_runs(const void* sorted, uint64_t n, uint32_t rec_bytes, uint32_t key_bytes, void* uniq,
+                      uint64_t* counts, uint64_t* num_runs, void* stream);
+
+/* raduls_sort of `records` followed by raduls_count_runs on them: the
+ * distinct keys in ascending order with their multiplicities (k-mer
+ * counting, Sec. 5).  uniq may be `records`, `tmp` (free once the sort is
+ * done) or a buffer apart from both; records keep the sorted order unless
+ * uniq is `records`. */
+int raduls_sort_count(void* records, void* tmp, uint64_t n, uint32_t rec_bytes, uint32_t key_bytes, void* uniq,
+                      uint64_t* counts, uint64_t* num_runs, void* stream);
+
 /* Wait for `stream` and report device-side failures of earlier calls on this
  * device (RADULS_EDEVICE: invalid segment offsets).  Clears the flags. */
 int raduls_sync_check(void* stream);

@@ -66,6 +66,8 @@ struct DeviceState {
   std::vector<int> ph_id;
   bool ph_valid = false;
   int cu_count = 256;
+  uint8_t* runs_ws = nullptr;     // run counting: control block + look-back words
+  size_t runs_bytes = 0;
 };
 
 std::map<int, DeviceState> g_dev;
@@ -98,6 +100,12 @@ int hip_fail(hipError_t e, const char* where) {
 bool overlap(const void* a, const void* b, uint64_t bytes) {
   uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
   return x < y + bytes && y < x + bytes;
+}
+
+// [a, a + na) and [b, b + nb) share a byte
+bool overlap2(const void* a, uint64_t na, const void* b, uint64_t nb) {
+  uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+  return x < y + nb && y < x + na;
 }
 
 int check_shape(uint32_t r, uint32_t k) {
@@ -558,6 +566,63 @@ int check_ctl(rd::Ctl* ctl) {
   return fail(RADULS_EDEVICE, "a device queue overflowed");
 }
 
+// Workspace of the run-counting pass, grown on demand.
+int ensure_runs_workspace(DeviceState& s, uint64_t n, uint32_t rec_bytes) {
+  const size_t want = rd::runs_workspace_bytes(n, rec_bytes);
+  if (want <= s.runs_bytes) return RADULS_OK;
+  if (s.runs_ws) {
+    HIPCHK(hipDeviceSynchronize());
+    hipFree(s.runs_ws);
+    s.runs_ws = nullptr;
+    s.runs_bytes = 0;
+  }
+  const size_t bytes = want + want / 8;
+  if (hipMalloc(&s.runs_ws, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    s.runs_ws = nullptr;
+    return fail(RADULS_ENOMEM, "run-counting workspace allocation failed");
+  }
+  s.runs_bytes = bytes;
+  return RADULS_OK;
+}
+
+// Arguments of the run-counting pass: `uniq` is `sorted` itself or apart
+// from it; counts and num_runs apart from both.
+int check_runs_args(const void* sorted, uint64_t n, uint32_t r, const void* uniq, const uint64_t* counts,
+                    const uint64_t* num_runs) {
+  if (!num_runs) return fail(RADULS_EINVAL, "null num_runs");
+  if ((uintptr_t)num_runs & 7) return fail(RADULS_EINVAL, "num_runs must be 8-byte aligned");
+  if (n == 0) return RADULS_OK;
+  if (!sorted || !uniq || !counts) return fail(RADULS_EINVAL, "null pointer");
+  if (n >= (1ull << 40)) return fail(RADULS_EUNSUPPORTED, "n must be below 2^40");
+  if (rd::runs_tiles(n, r) >= (1ull << 24)) return fail(RADULS_EUNSUPPORTED, "too many records for one pass");
+  if (((uintptr_t)sorted & 15) || ((uintptr_t)uniq & 15)) return fail(RADULS_EINVAL, "buffers must be 16-byte aligned");
+  if ((uintptr_t)counts & 7) return fail(RADULS_EINVAL, "counts must be 8-byte aligned");
+  const uint64_t rb = n * r, cb = n * 8;
+  if (uniq != sorted && overlap(uniq, sorted, rb)) return fail(RADULS_EINVAL, "uniq overlaps the records partly");
+  if (overlap2(counts, cb, sorted, rb) || overlap2(counts, cb, uniq, rb))
+    return fail(RADULS_EINVAL, "counts overlaps the records");
+  if (overlap2(num_runs, 8, sorted, rb) || overlap2(num_runs, 8, uniq, rb) || overlap2(num_runs, 8, counts, cb))
+    return fail(RADULS_EINVAL, "num_runs overlaps another buffer");
+  return RADULS_OK;
+}
+
+int enqueue_runs(const void* sorted, uint64_t n, uint32_t r, uint32_t k, void* uniq, uint64_t* counts,
+                 uint64_t* num_runs, hipStream_t st) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  DeviceState& s = state_for(dev);
+  int rc = order_after_previous(s, st);
+  if (rc) return rc;
+  rc = ensure_runs_workspace(s, n, r);
+  if (rc) return rc;
+  uint32_t spin = 1u << 16;
+  if (const char* e = getenv("RADULS_TEST_SPIN_LIMIT")) spin = (uint32_t)strtoul(e, nullptr, 10);
+  rd::launch_runs(sorted, n, r, k, uniq, counts, num_runs, s.runs_ws, spin, st);
+  HIPCHK(hipGetLastError());
+  return mark_done(s, st);
+}
+
 }  // namespace
 
 extern "C" {
@@ -754,6 +819,38 @@ int raduls_partition(const void* in, void* out, uint64_t n, uint32_t rec_bytes, 
   return mark_done(s, st);
 }
 
+int raduls_count_runs(const void* sorted, uint64_t n, uint32_t rec_bytes, uint32_t key_bytes, void* uniq,
+                      uint64_t* counts, uint64_t* num_runs, void* stream) {
+  int rc = check_shape(rec_bytes, key_bytes);
+  if (rc) return rc;
+  rc = check_runs_args(sorted, n, rec_bytes, uniq, counts, num_runs);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lock(g_mu);
+  return enqueue_runs(sorted, n, rec_bytes, key_bytes, uniq, counts, num_runs, (hipStream_t)stream);
+}
+
+int raduls_sort_count(void* records, void* tmp, uint64_t n, uint32_t rec_bytes, uint32_t key_bytes, void* uniq,
+                      uint64_t* counts, uint64_t* num_runs, void* stream) {
+  int rc = check_shape(rec_bytes, key_bytes);
+  if (rc) return rc;
+  rc = check_runs_args(records, n, rec_bytes, uniq, counts, num_runs);
+  if (rc) return rc;
+  if (n > 0) {
+    if (!tmp) return fail(RADULS_EINVAL, "null tmp");
+    const uint64_t rb = n * rec_bytes;
+    if (uniq != tmp && overlap(uniq, tmp, rb)) return fail(RADULS_EINVAL, "uniq overlaps tmp partly");
+    if (overlap2(counts, n * 8, tmp, rb)) return fail(RADULS_EINVAL, "counts overlaps tmp");
+    if (overlap2(num_runs, 8, tmp, rb)) return fail(RADULS_EINVAL, "num_runs overlaps tmp");
+    if (overlap(records, tmp, rb)) return fail(RADULS_EINVAL, "records and tmp overlap");
+  }
+  if (n > 1) {
+    rc = raduls_sort(records, tmp, n, rec_bytes, key_bytes, stream);
+    if (rc) return rc;
+  }
+  std::lock_guard<std::mutex> lock(g_mu);
+  return enqueue_runs(records, n, rec_bytes, key_bytes, uniq, counts, num_runs, (hipStream_t)stream);
+}
+
 int raduls_last_work(uint64_t* host_out, uint32_t count) {
   if (!host_out) return fail(RADULS_EINVAL, "null pointer");
   std::lock_guard<std::mutex> lock(g_mu);
@@ -809,6 +906,15 @@ int raduls_sync_check(void* stream) {
   int rc = RADULS_OK;
   auto it = g_dev.find(dev);
   if (it != g_dev.end() && it->second.base) rc = check_ctl(it->second.work.ctl);
+  if (it != g_dev.end() && it->second.runs_ws) {
+    rd::RunCtl c;
+    HIPCHK(hipMemcpy(&c, it->second.runs_ws, sizeof(c), hipMemcpyDeviceToHost));
+    if (c.error) {
+      const uint32_t zero = 0;
+      HIPCHK(hipMemcpy(it->second.runs_ws + offsetof(rd::RunCtl, error), &zero, 4, hipMemcpyHostToDevice));
+      if (rc == RADULS_OK) rc = fail(RADULS_EDEVICE, "run counting: look-back wait limit reached");
+    }
+  }
   if (dev >= 0 && dev < NOALLOC_MAX_DEVICES && g_noalloc[dev].ctl) {
     int rc2 = check_ctl(g_noalloc[dev].ctl);
     if (rc == RADULS_OK) rc = rc2;
@@ -1025,6 +1131,7 @@ void raduls_release(void) {
     drop_graphs(s);
     if (s.base) hipFree(s.base);
     if (s.status_base) hipFree(s.status_base);
+    if (s.runs_ws) hipFree(s.runs_ws);
     if (s.model) hipFree(s.model);
     if (s.last_done) hipEventDestroy(s.last_done);
     if (s.t0) hipEventDestroy(s.t0);

@@ -24,6 +24,13 @@ void launch_small_jobs(const Plan& p, const Work& w, void* records, void* tmp, h
 void launch_fin_jobs(const Plan& p, const Work& w, void* records, void* tmp, hipStream_t s);
 void launch_copy(const Plan& p, const Work& w, void* records, const void* tmp, hipStream_t s);
 
+// runs of equal keys in key-ordered records (k_count.hip); the workspace
+// holds the control block and the look-back words
+size_t runs_workspace_bytes(uint64_t n, uint32_t rec_bytes);
+uint64_t runs_tiles(uint64_t n, uint32_t rec_bytes);
+void launch_runs(const void* src, uint64_t n, uint32_t rec_bytes, uint32_t key_bytes, void* uniq, uint64_t* counts,
+                 uint64_t* num_runs, void* ws, uint32_t spin_limit, hipStream_t s);
+
 // scheduler network
 void launch_mlp_forward(const float* X, const float* theta, float* Y, uint32_t B, hipStream_t s);
 void launch_mlp_loss_grad(const float* X, const float* T, const float* M, const float* theta, float* grad,

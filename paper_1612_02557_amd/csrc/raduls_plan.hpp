@@ -67,6 +67,12 @@ struct Ctl {
   unsigned long long stage_records[4];
 };
 
+// Control block of the run-counting pass (k_count.hip), zeroed per call.
+struct RunCtl {
+  uint32_t ticket;  // tiles handed out
+  uint32_t error;   // bit 0: look-back wait limit (the outputs are incomplete)
+};
+
 struct Plan {
   uint64_t n;              // records in all
   uint64_t t_big;          // buckets above this are multi-workgroup (Sec. 3.2: 2N/3T)

@@ -76,6 +76,8 @@ _SIGS = {
     "raduls_tune": (_i32, [_u32, _u32, _u64, _vp]),
     "raduls_sort_segmented": (_i32, [_vp, _vp, _vp, _u32, _u64, _u32, _u32, _vp]),
     "raduls_partition": (_i32, [_vp, _vp, _u64, _u32, _u32, _u32, _u32, _vp, _vp]),
+    "raduls_count_runs": (_i32, [_vp, _u64, _u32, _u32, _vp, _vp, _vp, _vp]),
+    "raduls_sort_count": (_i32, [_vp, _vp, _u64, _u32, _u32, _vp, _vp, _vp, _vp]),
     "raduls_sync_check": (_i32, [_vp]),
     "raduls_set_scheduler": (_i32, [_i32, _i32]),
     "raduls_get_scheduler": (_i32, [ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
@@ -239,6 +241,63 @@ def partition(inp, out, key_bytes: int, shift: int, bits: int, counts=None, stre
     _check(lib().raduls_partition(inp.data_ptr(), out.data_ptr(), n, r, key_bytes, shift, bits, cp,
                                   _stream(stream)))
     return out
+
+
+def _runs_outputs(records, uniq, counts, stream):
+    import torch
+    n = records.shape[0]
+    with torch.cuda.stream(_torch_stream(stream)):
+        if uniq is None:
+            uniq = torch.empty_like(records)
+        if counts is None:
+            counts = torch.empty(n, dtype=torch.int64, device=records.device)
+        num = torch.empty(1, dtype=torch.int64, device=records.device)
+    uniq = _records(uniq)
+    if uniq.shape[0] < n or uniq.shape[1] != records.shape[1]:
+        raise ValueError("uniq must hold as many records of the same size")
+    if not counts.is_cuda or counts.element_size() != 8 or not counts.is_contiguous() or counts.numel() < n:
+        raise ValueError("counts must be a contiguous 8-byte CUDA tensor of at least n entries")
+    return uniq, counts, num
+
+
+def _runs_result(uniq, counts, num, stream, check):
+    _torch_stream(stream).synchronize()
+    if check:
+        sync_check(stream)
+    u = int(num.item())
+    return uniq[:u], counts[:u]
+
+
+def count_runs(sorted_records, key_bytes: int, uniq=None, counts=None, stream=None, check: bool = False):
+    """Runs of equal keys in key-ordered records (``raduls_count_runs``):
+    returns (first record of each run, run lengths) as views of ``uniq`` and
+    ``counts`` (allocated when not given; ``uniq`` may be the input)."""
+    rec = _records(sorted_records)
+    n, r = rec.shape
+    uniq, counts, num = _runs_outputs(rec, uniq, counts, stream)
+    _check(lib().raduls_count_runs(rec.data_ptr(), n, r, key_bytes, uniq.data_ptr(), counts.data_ptr(),
+                                   num.data_ptr(), _stream(stream)))
+    return _runs_result(uniq, counts, num, stream, check)
+
+
+def sort_count(records, key_bytes: int, tmp=None, uniq=None, counts=None, stream=None, check: bool = False):
+    """Sort ``records`` in place, then count its runs (``raduls_sort_count``):
+    the distinct keys in ascending order with their multiplicities.  ``uniq``
+    may be ``records`` or ``tmp``."""
+    rec = _records(records)
+    n, r = rec.shape
+    if tmp is None:
+        tmp = _scratch_like(rec, stream)
+    uniq, counts, num = _runs_outputs(rec, uniq, counts, stream)
+    _check(lib().raduls_sort_count(rec.data_ptr(), tmp.data_ptr(), n, r, key_bytes, uniq.data_ptr(),
+                                   counts.data_ptr(), num.data_ptr(), _stream(stream)))
+    return _runs_result(uniq, counts, num, stream, check)
+
+
+def count_runs_ptr(sorted_ptr: int, n: int, rec_bytes: int, key_bytes: int, uniq_ptr: int, counts_ptr: int,
+                   num_ptr: int, stream: int) -> int:
+    """Raw call returning the status code (for argument-error tests)."""
+    return lib().raduls_count_runs(sorted_ptr, n, rec_bytes, key_bytes, uniq_ptr, counts_ptr, num_ptr, stream)
 
 
 def sync_check(stream=None):

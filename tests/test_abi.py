@@ -158,3 +158,23 @@ def test_noalloc_validation(R):
     assert f(p, p + 800, 100, 16, 8, 0) == R.EINVAL                # records and tmp overlap
     assert f(p + 4, p + (1 << 30), 100, 16, 8, 0) == R.EINVAL      # misaligned
     assert f(0, 0, 1, 16, 8, 0) == R.OK                            # n <= 1: nothing to do
+
+
+def test_count_runs_validation(R):
+    p = 1 << 20
+    G = 1 << 30
+    ok_args = (p, 100, 16, 8, p + G, p + 2 * G, p + 3 * G, 0)
+    call = R.count_runs_ptr
+    assert call(p, 100, 6, 4, p + G, p + 2 * G, p + 3 * G, 0) == R.EUNSUPPORTED       # rec_bytes % 4
+    assert call(p, 100, 16, 0, p + G, p + 2 * G, p + 3 * G, 0) == R.EINVAL            # key_bytes == 0
+    assert call(p, 100, 16, 8, p + G, p + 2 * G, 0, 0) == R.EINVAL                    # null num_runs
+    assert call(0, 100, 16, 8, p + G, p + 2 * G, p + 3 * G, 0) == R.EINVAL            # null records
+    assert call(p, 100, 16, 8, p + G, 0, p + 3 * G, 0) == R.EINVAL                    # null counts
+    assert call(p, 100, 16, 8, p + 16, p + 2 * G, p + 3 * G, 0) == R.EINVAL           # uniq overlaps partly
+    assert call(p, 100, 16, 8, p + G, p + 800, p + 3 * G, 0) == R.EINVAL              # counts inside records
+    assert call(p, 100, 16, 8, p + G, p + 2 * G, p + 2 * G + 8, 0) == R.EINVAL        # num_runs inside counts
+    assert call(p + 4, 100, 16, 8, p + G, p + 2 * G, p + 3 * G, 0) == R.EINVAL        # misaligned records
+    assert call(p, 100, 16, 8, p + G, p + 2 * G + 4, p + 3 * G, 0) == R.EINVAL        # misaligned counts
+    assert call(p, 1 << 40, 16, 8, p + G, p + 2 * G, p + 3 * G, 0) == R.EUNSUPPORTED
+    assert ok_args[0] == p
+
