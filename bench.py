@@ -9,7 +9,16 @@ pristine copy, and copied into the working buffer before every step
 (outside the timed region), so every timed step sorts the same unsorted
 input that is already resident in HBM.
 
-Prints one JSON line (see the design doc for the fields).
+Prints one JSON line: the metric, records/s, ms per step, the roofline of
+the kernel with the most time per step (algorithmic bytes per launch over
+its average launch time, against the 8 TB/s HBM peak), the end-to-end
+fraction of the byte model, per-pass rates, the learned-scheduler leg and
+the CPU oracle baseline.
+
+Other legs: --batched (many independent arrays in one call vs one call per
+array), --kmer (k-mer counting: sort + duplicate removal with counts, at the
+sizes of the paper's three k-mer sets), --autotune (the autotuner's tuning
+for the workload's shape against the defaults).
 """
 from __future__ import annotations
 
@@ -212,6 +221,20 @@ def batched_main(args):
     err = batched_check(rec, off, sizes, dists, spec, tmp, S)
     if err:
         log(f"VERIFICATION FAILED: {err}")
+    tuned_leg = None
+    if args.autotune:
+        t0 = time.perf_counter()
+        tuned = raduls.tune(16, 8, n)
+        tune_s = time.perf_counter() - t0
+        timed(batched)
+        tt = [timed(batched) for _ in range(args.steps)]
+        raduls.sync_check()
+        terr = batched_check(rec, off, sizes, dists, spec, tmp, S)
+        mt = statistics.median(tt)
+        tuned_leg = {"ms_per_step": mt, "value": n / (mt / 1e3), "default_over_tuned": statistics.median(tb) / mt,
+                     "tuning": tuned.as_dict(), "tune_seconds": tune_s, "verified": terr is None, "step_ms": tt}
+        log(f"batched, autotuned: {mt:.2f} ms")
+        raduls.set_tuning(None)
     timed(per_array)
     tp = [timed(per_array) for _ in range(max(1, args.steps // 2))]
     mb, mp = statistics.median(tb), statistics.median(tp)
@@ -223,7 +246,99 @@ def batched_main(args):
                                   f"[{args.seg_lo}, {args.seg_hi}], uniform or Zipf keys per array (seed {args.seed})",
                       "segments": S, "records": n},
            "per_array_ms": mp, "per_array_value": n / (mp / 1e3), "batched_over_per_array": mp / mb,
-           "verified": err is None, "step_ms": tb, "per_array_step_ms": tp}
+           "verified": err is None, "step_ms": tb, "per_array_step_ms": tp, "autotuned": tuned_leg}
+    print(json.dumps(out), flush=True)
+
+
+def kmer_main(args):
+    """k-mer counting (paper, Sec. 5): records of 16 bytes whose 16-byte keys
+    are 64-base k-mers of synthetic reads (one genome, coverage 16, one base
+    in 64 records substituted), sorted and reduced to distinct k-mers with
+    counts by raduls_sort_count, at the record counts of the paper's three
+    k-mer sets.  Timed with HIP events on the stream the library uses; the
+    run-counting kernel is also timed alone on the sorted records."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1612_02557_amd import raduls
+    from synth import device as sdev
+    raduls.lib()
+    raduls.set_scheduler(raduls.SCHED_HEURISTIC)
+    raduls.set_timing(0)
+    sizes = [int(x) for x in args.kmer_sizes.split(",")]
+    legs = []
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    for n in sizes:
+        spec = synth.Spec(n=n, rec_bytes=16, key_bytes=16, dist="kmer", payload="index", seed=args.seed)
+        log(f"k-mers: generating {n} records")
+        pristine = sdev.generate(spec)
+        rec = torch.empty_like(pristine)
+        tmp = torch.empty_like(pristine)
+        counts = torch.empty(n, dtype=torch.int64, device="cuda")
+        num = torch.empty(1, dtype=torch.int64, device="cuda")
+        st = torch.cuda.current_stream().cuda_stream
+        L = raduls.lib()
+
+        def timed(fn):
+            rec.copy_(pristine)
+            torch.cuda.synchronize()
+            ev[0].record()
+            fn()
+            ev[1].record()
+            torch.cuda.synchronize()
+            return ev[0].elapsed_time(ev[1])
+
+        def sort_count():
+            raduls._check(L.raduls_sort_count(rec.data_ptr(), tmp.data_ptr(), n, 16, 16, tmp.data_ptr(),
+                                              counts.data_ptr(), num.data_ptr(), st))
+
+        for _ in range(args.warmup):
+            timed(sort_count)
+        t_all = [timed(sort_count) for _ in range(args.steps)]
+        raduls.sync_check()
+        U = int(num.item())
+        # the run-counting kernel alone, on the sorted records now in `rec`
+        raduls.sort(rec, 16, tmp)
+        torch.cuda.synchronize()
+        t_runs = []
+        for _ in range(args.steps + 1):
+            ev[0].record()
+            raduls._check(L.raduls_count_runs(rec.data_ptr(), n, 16, 16, tmp.data_ptr(), counts.data_ptr(),
+                                              num.data_ptr(), st))
+            ev[1].record()
+            torch.cuda.synchronize()
+            t_runs.append(ev[0].elapsed_time(ev[1]))
+        t_runs = t_runs[1:]
+        raduls.sync_check()
+        # checks that hold at any size: counts sum to n, positive, keys increase
+        c = counts[:U]
+        w = tmp[:U].view(torch.int64).view(U, 2)
+        hi, lo = w[:, 1] ^ torch.iinfo(torch.int64).min, w[:, 0] ^ torch.iinfo(torch.int64).min
+        inc = (hi[1:] > hi[:-1]) | ((hi[1:] == hi[:-1]) & (lo[1:] > lo[:-1]))
+        ok = int(c.sum().item()) == n and int(c.min().item()) >= 1 and bool(inc.all().item())
+        ms, mr = statistics.median(t_all), statistics.median(t_runs)
+        runs_bytes = 16 * n + U * (16 + 8)
+        legs.append({"n": n, "distinct": U, "ms_sort_count": ms, "kmers_per_s": n / (ms / 1e3),
+                     "ms_count_runs": mr, "count_runs_alg_bytes": runs_bytes,
+                     "count_runs_GBps": runs_bytes / mr / 1e6, "count_runs_frac": runs_bytes / mr / 1e6 / HBM_PEAK_GBPS,
+                     "sort_share": 1.0 - mr / ms, "verified": ok, "step_ms": t_all})
+        log(f"k-mers n={n}: {ms:.2f} ms sort+count ({U} distinct), count alone {mr:.3f} ms")
+        del pristine, rec, tmp, counts, num, c, w, hi, lo, inc
+        torch.cuda.empty_cache()
+    big = legs[-1]
+    out = {"metric": "k-mers counted per second (sort + duplicate removal with counts), 16-byte k-mer records",
+           "value": big["kmers_per_s"], "unit": "records/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": big["ms_sort_count"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "u128", "data": "synthetic",
+           "config": {"workload": "count the distinct 64-base k-mers (16-byte keys, 16-byte records) of synthetic "
+                                  "reads of one genome, coverage 16, 1/64 records with a substituted base, at the "
+                                  "record counts of the paper's three k-mer sets", "sizes": sizes,
+                      "seed": args.seed},
+           "roofline": {"bound": "hbm", "kernel": "k_runs", "achieved": big["count_runs_GBps"],
+                        "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": big["count_runs_frac"], "traffic": None,
+                        "alg_bytes_per_launch": big["count_runs_alg_bytes"], "avg_launch_ms": big["ms_count_runs"]},
+           "legs": legs, "verified": all(l_["verified"] for l_ in legs)}
     print(json.dumps(out), flush=True)
 
 
@@ -247,15 +362,21 @@ def main():
     ap.add_argument("--segs", type=int, default=10000)
     ap.add_argument("--seg-lo", type=int, default=1 << 10)
     ap.add_argument("--seg-hi", type=int, default=1 << 22)
+    ap.add_argument("--kmer", action="store_true", help="k-mer counting: sort + duplicate removal with counts")
+    ap.add_argument("--kmer-sizes", default="63000000,413000000,1887000000")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time the autotuner's tuning for this shape against the defaults")
     args = ap.parse_args()
 
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              f"(the batched and single-array paths are single-GPU; see DESIGN.md for sharding)", file=sys.stderr)
+              f"(the batched and single-array paths are single-GPU)", file=sys.stderr)
         sys.exit(2)
 
     if args.batched:
         return batched_main(args)
+    if args.kmer:
+        return kmer_main(args)
 
     import torch
 
@@ -401,7 +522,23 @@ def main():
         "timed_wall_s": wall,
         "verified": verified,
     }
-    # learned scheduler on the same input (the committed trained network)
+    # the autotuner's tuning for this shape, heuristic scheduler
+    autotuned = None
+    if args.autotune and not args.tuning:
+        raduls.set_timing(1)
+        t0 = time.perf_counter()
+        tuned = raduls.tune(r, k, n)
+        tune_s = time.perf_counter() - t0
+        step()
+        at = [step() for _ in range(args.steps)]
+        aerr = exact_index_check(rec, pristine, r, k)
+        ams = statistics.mean(at)
+        autotuned = {"ms_per_step": ams, "value": n / (ams / 1e3), "default_over_tuned": ms_per_step / ams,
+                     "tuning": tuned.as_dict(), "default": raduls.default_tuning(r, k, n).as_dict(),
+                     "tune_seconds": tune_s, "verified": None if aerr == "unchecked" else aerr is None}
+        log(f"autotuned: {ams:.3f} ms per step (tuning took {tune_s:.1f} s)")
+    # learned scheduler on the same input (the committed trained network),
+    # with the autotuned tuning when --autotune ran
     learned = None
     model = os.path.join(ROOT, "paper_1612_02557_amd", "models", "sched_mlp.rdls")
     if not args.no_learned and os.path.exists(model):
@@ -421,6 +558,7 @@ def main():
                    "model": "paper_1612_02557_amd/models/sched_mlp.rdls"}
         log(f"learned scheduler: {lms:.3f} ms per step")
     out["learned"] = learned
+    out["autotuned"] = autotuned
     del tmp, rec
     torch.cuda.empty_cache()
     if not args.no_cpu:

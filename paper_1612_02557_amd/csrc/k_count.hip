@@ -11,7 +11,8 @@
 // flags (ballots per wavefront row), the number of heads h and the index of
 // its last head; the heads before the tile (H) and the last head before it
 // (P) come from a decoupled look-back over the tiles' (h, last head) pairs,
-// combined as (H1 + H2, last2 if the second part has a head, else last1).
+// combined as (H1 + H2, last2 if the second part has a head, else last1),
+// one wavefront reading 64 earlier tiles' words at a time.
 // Each head then writes its record to uniq[H + rank] and the length of the
 // run before it (its index minus the previous head's), so every count is
 // written exactly once, by a plain store; the tile holding the last record
@@ -28,11 +29,12 @@ namespace rd {
 namespace {
 
 // Look-back words, four per tile: the tile's own (heads, last head + 1) and
-// the inclusive pair of this and all earlier tiles.  A heads word is ready
-// when its top bit is set; its pair word is written before it (release
-// order), so a reader that saw the heads word ready reads the pair word
-// after it.  A tile that gave up on its wait publishes a poisoned inclusive
-// word, and tiles after it give up at once.
+// the inclusive pair of this and all earlier tiles.  Every word carries its
+// own ready bit (the top bit), so a pair is read as ready when both of its
+// words are, and the words are plain relaxed device-scope atomics: no cache
+// write-back or invalidation between the XCDs' L2s is needed.  A tile that
+// gave up on its wait publishes a poisoned inclusive pair, and tiles after
+// it give up at once.
 constexpr uint64_t RL_READY = 1ull << 63;
 constexpr uint64_t RL_POISON = 1ull << 62;
 constexpr uint64_t RL_VAL = RL_POISON - 1;
@@ -42,12 +44,12 @@ constexpr uint32_t runs_per_thread() {
   return RW <= 2 ? 16u : (32u / RW >= 2 ? 32u / RW : 2u);
 }
 
-__device__ __forceinline__ uint64_t load_acquire(const uint64_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ uint64_t wave_sum64(uint64_t x) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o);
+  return x;
 }
-__device__ __forceinline__ void store_release(uint64_t* p, uint64_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-}
+
 
 template <int RW>
 __global__ __launch_bounds__(WG) void k_runs(const uint8_t* src, uint64_t n, KeyFmt kf,
@@ -100,9 +102,13 @@ __global__ __launch_bounds__(WG) void k_runs(const uint8_t* src, uint64_t n, Key
       s_last[s] = hb[e] ? base + e * WG + wave * 64 + (63 - __clzll(hb[e])) + 1 : 0ull;
     }
   }
-  // every load of the tile completes before the tile publishes (uniq may be
-  // the input: later tiles write below their heads only after that)
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  // every load of the tile has returned before the tile publishes (uniq may
+  // be the input: later tiles write below their heads only after that)
+#pragma unroll
+  for (uint32_t e = 0; e < E; e++) {
+#pragma unroll
+    for (int q = 0; q < RW; q++) asm volatile("" : : "v"(rec[e].w[q]));
+  }
   __syncthreads();
 
   if (wave == 0) {
@@ -123,48 +129,73 @@ __global__ __launch_bounds__(WG) void k_runs(const uint8_t* src, uint64_t n, Key
     if (lane == 0) exl = 0;
     if (lane < NS) { s_cnt[lane] = ex; s_last[lane] = exl; }
 
-    if (lane == 0) {
-      const uint64_t h = tot;
-      uint64_t* my = st + 4 * tile;
-      uint64_t H = 0, P = 0;
-      bool ok = true;
-      if (tile == 0) {
-        atomic_store_agent(&my[3], lp);
-        store_release(&my[2], RL_READY | h);
-      } else {
-        atomic_store_agent(&my[1], lp);
-        store_release(&my[0], RL_READY | h);
-        uint64_t j = tile - 1;
-        uint32_t spins = 0;
-        for (;;) {
-          // bounded wait: past the limit the tile gives up, flags the error
-          // and poisons its inclusive word so that the tiles after it stop too
-          if (spins >= spin_limit) { ok = false; break; }
-          const uint64_t inc = load_acquire(&st[4 * j + 2]);
-          if (inc & RL_READY) {
-            if (inc & RL_POISON) { ok = false; break; }
-            H += inc & RL_VAL;
-            if (!P) P = atomic_load_agent(&st[4 * j + 3]);
-            break;
-          }
-          const uint64_t agg = load_acquire(&st[4 * j + 0]);
-          if (agg & RL_READY) {
-            H += agg & RL_VAL;
-            if (!P) P = atomic_load_agent(&st[4 * j + 1]);
-            --j;  // tile 0 publishes only an inclusive word, so j stays >= 0
-            continue;
-          }
+    const uint64_t h = tot;
+    uint64_t* my = st + 4 * tile;
+    uint64_t H = 0, P = 0;
+    bool ok = true;
+    if (tile == 0) {
+      if (lane == 0) {
+        atomic_store_agent(&my[3], RL_READY | lp);
+        atomic_store_agent(&my[2], RL_READY | h);
+      }
+    } else {
+      if (lane == 0) {
+        atomic_store_agent(&my[1], RL_READY | lp);
+        atomic_store_agent(&my[0], RL_READY | h);
+      }
+      // look back over a window of 64 earlier tiles at once (lane L reads
+      // tile j0 - L): the nearest tile with an inclusive word ends the walk
+      // when every tile between it and this one has published its own pair
+      uint64_t j0 = tile - 1;
+      uint32_t spins = 0;
+      bool done = false;
+      while (!done) {
+        // bounded wait: past the limit the tile gives up, flags the error
+        // and poisons its inclusive word so that the tiles after it stop too
+        if (spins >= spin_limit) { ok = false; break; }
+        const bool exists = j0 >= (uint64_t)lane;
+        const uint64_t j = exists ? j0 - lane : 0;
+        // before tile 0: an empty inclusive prefix
+        uint64_t w = exists ? atomic_load_agent(&st[4 * j + 2]) : RL_READY;
+        uint64_t pw = exists ? atomic_load_agent(&st[4 * j + 3]) : RL_READY;
+        const bool inc = (w & pw & RL_READY) != 0;
+        if (!inc) {
+          w = atomic_load_agent(&st[4 * j + 0]);
+          pw = atomic_load_agent(&st[4 * j + 1]);
+        }
+        const bool ready = (w & pw & RL_READY) != 0;
+        pw &= RL_VAL;
+        const uint64_t incm = __ballot(inc);
+        const uint64_t waiting = __ballot(!ready);
+        const uint32_t first = incm ? (uint32_t)(__ffsll((long long)incm) - 1) : 64u;
+        const uint64_t below = first >= 63 ? ~0ull : ((2ull << first) - 1);  // lanes 0..first
+        if (waiting & below) {  // a tile before the nearest inclusive one is not ready
           ++spins;
           __builtin_amdgcn_s_sleep(1);
+          continue;
         }
+        if (first < 64 && __shfl(w, (int)first) & RL_POISON) { ok = false; break; }
+        const bool use = lane <= first;
+        H += wave_sum64(use ? (w & RL_VAL) : 0ull);
+        if (!P) {
+          const uint64_t pm = __ballot(use && pw != 0);
+          if (pm) P = __shfl(pw, (int)(__ffsll((long long)pm) - 1));
+        }
+        done = first < 64;
+        j0 -= 64;
+      }
+      if (lane == 0) {
         if (ok) {
-          atomic_store_agent(&my[3], lp ? lp : P);
-          store_release(&my[2], RL_READY | (H + h));
+          atomic_store_agent(&my[3], RL_READY | (lp ? lp : P));
+          atomic_store_agent(&my[2], RL_READY | (H + h));
         } else {
           atomicOr(&ctl->error, 1u);
-          store_release(&my[2], RL_READY | RL_POISON);
+          atomic_store_agent(&my[3], RL_READY);
+          atomic_store_agent(&my[2], RL_READY | RL_POISON);
         }
       }
+    }
+    if (lane == 0) {
       s_H = H;
       s_P = P;
       s_ok = ok ? 1u : 0u;

@@ -9,7 +9,7 @@ bucket, and the sorter takes the cheapest feasible one:
    jobs run every feasible procedure (after one untimed warm-up run) and
    record each one's time, the others record the time of the procedure that
    ran.  Rows come from the library (64 bytes each).
-2. ``train``: masked least squares on log2(ticks), by the library's own
+2. ``train``: masked least squares on log2(ticks) of the sampled rows, by the library's own
    kernels (``raduls_mlp_loss_grad``, ``raduls_mlp_adam``); this module only
    batches tensors.
 3. ``regret`` on held-out sampled rows for the learned choice and for the
@@ -18,7 +18,8 @@ bucket, and the sorter takes the cheapest feasible one:
 
 ``python -m paper_1612_02557_amd.learn --out DIR`` runs all four on the
 current GPU and writes ``DIR/sched_mlp.rdls`` (the blob ``raduls_load_model``
-takes) and ``DIR/learn_report.json``.
+takes), ``DIR/learn_report.json`` and ``DIR/sched_holdout.npz`` (a subset of
+the held-out sampled rows, for an offline regret check).
 """
 from __future__ import annotations
 
@@ -36,6 +37,7 @@ from . import raduls
 F, H, P = raduls.MLP_F, raduls.MLP_H, raduls.MLP_P
 ROW = np.dtype([("features", "<f4", (9,)), ("chosen", "<u4"), ("count", "<u4"), ("observed", "<u4"),
                 ("ticks", "<u4", (3,)), ("flags", "<u4")])
+OOD_Z = 4.0  # RADULS_MLP_OOD_Z
 MODEL_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "models", "sched_mlp.rdls")
 
 # (log2 n, rec_bytes, key_bytes, distribution) of the training workloads:
@@ -83,7 +85,14 @@ def collect(workloads, sample_period=3, seed=100, cap=1 << 21, per_workload=None
 
 
 def dataset(tr):
-    """Features, log2-time targets and masks of trace rows."""
+    """Features, log2-time targets and masks of the sampled trace rows.
+
+    Only sampled rows are used: each of them timed every feasible procedure
+    under the same conditions (its input copied to tmp, one untimed run
+    first).  The other rows time only the procedure the running scheduler
+    chose, under other conditions (records already staged, the next job's
+    loads in flight), so their targets would be confounded with that choice."""
+    tr = tr[(tr["flags"] & 1) != 0]
     X = tr["features"].astype(np.float32)
     obs = tr["observed"].astype(np.uint32)
     M = np.stack([(obs >> q) & 1 for q in range(P)], axis=1).astype(np.float32)
@@ -163,13 +172,30 @@ def evaluate(theta, mean, scale, tr):
     if len(s) == 0:
         return {"rows": 0}
     feas = s["observed"].astype(np.uint32)
-    Y = predict(theta, mean, scale, s["features"].astype(np.float32))
+    X = s["features"].astype(np.float32)
+    Y = predict(theta, mean, scale, X)
     learned = masked_argmin(Y, feas)
+    # outside the training range the sorter keeps the heuristic's choice
+    ood = np.abs((X - mean) / scale).max(axis=1) > OOD_Z
+    learned = np.where(ood, s["chosen"].astype(np.int64), learned)
     return {"rows": int(len(s)),
             "regret_learned": regret(learned, s["ticks"], feas),
             "regret_heuristic": regret(s["chosen"].astype(np.int64), s["ticks"], feas),
             "learned_picks": np.bincount(learned, minlength=P).tolist(),
+            "out_of_range_rows": int(ood.sum()),
             "heuristic_picks": np.bincount(s["chosen"].astype(np.int64), minlength=P).tolist()}
+
+
+def save_fixture(tr, path, rows=6000, seed=11):
+    """A random subset of the sampled held-out rows (features, feasible set,
+    per-procedure ticks, the heuristic's choice, job size), for an offline
+    check of the trained network's regret."""
+    s = tr[(tr["flags"] & 1) != 0]
+    if len(s) > rows:
+        s = s[np.sort(np.random.default_rng(seed).choice(len(s), rows, replace=False))]
+    np.savez_compressed(path, features=s["features"].astype(np.float32), observed=s["observed"].astype(np.uint32),
+                        ticks=s["ticks"].astype(np.uint32), chosen=s["chosen"].astype(np.uint32),
+                        count=s["count"].astype(np.uint32), flags=s["flags"].astype(np.uint32))
 
 
 def compare(blob, configs, reps=5, seed=500):
@@ -226,6 +252,7 @@ def main(argv=None):
     blob = raduls.model_blob(theta, mean, scale)
     with open(os.path.join(args.out, "sched_mlp.rdls"), "wb") as f:
         f.write(blob)
+    save_fixture(ho, os.path.join(args.out, "sched_holdout.npz"))
     ev_train = evaluate(theta, mean, scale, tr)
     ev_hold = evaluate(theta, mean, scale, ho)
     per = []
