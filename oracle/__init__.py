@@ -12,6 +12,8 @@ path (``paper_1612_02557_amd``) never does, and shares no code with it.
   gradients and Adam step.
 * ``sched_ref`` (Python): the heuristic procedure rules restated from the
   paper's thresholds (Sec. 3.2-3.5), and the regret of a choice.
+* ``search_ref`` (Python): the suffix array of a text and the suffix-array
+  range of each k-character query prefix (pattern search, Sec. 5).
 """
 from .sort_ref import (  # noqa: F401
     lib,
