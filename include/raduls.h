@@ -184,6 +184,35 @@ int raduls_count_runs(const void* sorted, uint64_t n, uint32_t rec_bytes, uint32
 int raduls_sort_count(void* records, void* tmp, uint64_t n, uint32_t rec_bytes, uint32_t key_bytes, void* uniq,
                       uint64_t* counts, uint64_t* num_runs, void* stream);
 
+/* Pattern-prefix search over a suffix array (paper, Sec. 5: patterns are
+ * looked up in a suffix array by binary search; with the patterns, or their
+ * prefixes, sorted first, the searches run in narrowed ranges).
+ * text (device, text_len bytes, 1 <= text_len < 2^32): the text; sa (device,
+ * text_len uint32): its suffix array, i.e. the suffix start positions in
+ * lexicographic order (any order in which the k-prefixes defined below do
+ * not decrease will do).  queries (device, nq records of rec_bytes, 16-byte
+ * aligned): the key of query i (key_bytes = k <= 16 bytes) holds k pattern
+ * characters reversed -- key byte k-1 is the first character -- so that key
+ * order is string order.  The k-prefix of suffix j is text[j, j+k) with
+ * zero bytes past the end of the text.  lo[i] (device uint64) receives the
+ * number of suffixes whose k-prefix is below query i's characters and hi[i]
+ * the number at or below them: sa[lo[i], hi[i]) are the suffixes that start
+ * with them.  Results do not depend on the query order; queries in
+ * ascending key order (as raduls_sort leaves them) are searched in ranges
+ * narrowed per 256 consecutive queries, unless `flags` holds
+ * RADULS_SEARCH_NO_NARROWING (every query searched over the whole array).
+ * lo and hi overlap nothing.  Stream-ordered; allocates nothing. */
+#define RADULS_SEARCH_NO_NARROWING 1u
+int raduls_prefix_search(const void* text, uint64_t text_len, const uint32_t* sa, const void* queries, uint64_t nq,
+                         uint32_t rec_bytes, uint32_t key_bytes, uint64_t* lo, uint64_t* hi, uint32_t flags,
+                         void* stream);
+
+/* raduls_sort of the query records (stable, by key) followed by
+ * raduls_prefix_search on them: lo/hi follow the sorted order, and a
+ * payload carrying each pattern's id maps them back. */
+int raduls_sort_search(void* queries, void* tmp, uint64_t nq, uint32_t rec_bytes, uint32_t key_bytes, const void* text,
+                       uint64_t text_len, const uint32_t* sa, uint64_t* lo, uint64_t* hi, void* stream);
+
 /* Wait for `stream` and report device-side failures of earlier calls on this
  * device (RADULS_EDEVICE: invalid segment offsets).  Clears the flags. */
 int raduls_sync_check(void* stream);

@@ -851,6 +851,44 @@ int raduls_sort_count(void* records, void* tmp, uint64_t n, uint32_t rec_bytes, 
   return enqueue_runs(records, n, rec_bytes, key_bytes, uniq, counts, num_runs, (hipStream_t)stream);
 }
 
+int raduls_prefix_search(const void* text, uint64_t text_len, const uint32_t* sa, const void* queries, uint64_t nq,
+                         uint32_t rec_bytes, uint32_t key_bytes, uint64_t* lo, uint64_t* hi, uint32_t flags,
+                         void* stream) {
+  int rc = check_shape(rec_bytes, key_bytes);
+  if (rc) return rc;
+  if (flags & ~(uint32_t)RADULS_SEARCH_NO_NARROWING) return fail(RADULS_EINVAL, "unknown search flags");
+  if (nq == 0) return RADULS_OK;
+  if (!text || !sa || !queries || !lo || !hi) return fail(RADULS_EINVAL, "null pointer");
+  if (text_len == 0 || text_len > 0xFFFFFFFFull) return fail(RADULS_EUNSUPPORTED, "text length must be 1 .. 2^32-1");
+  if (nq >= (1ull << 40)) return fail(RADULS_EUNSUPPORTED, "nq must be below 2^40");
+  if (((uintptr_t)queries & 15)) return fail(RADULS_EINVAL, "queries must be 16-byte aligned");
+  if (((uintptr_t)sa & 3) || ((uintptr_t)lo & 7) || ((uintptr_t)hi & 7)) return fail(RADULS_EINVAL, "misaligned sa, lo or hi");
+  if (overlap2(lo, nq * 8, hi, nq * 8)) return fail(RADULS_EINVAL, "lo and hi overlap");
+  const uint64_t qb = nq * rec_bytes;
+  if (overlap2(lo, nq * 8, queries, qb) || overlap2(hi, nq * 8, queries, qb) || overlap2(lo, nq * 8, text, text_len) ||
+      overlap2(hi, nq * 8, text, text_len) || overlap2(lo, nq * 8, sa, text_len * 4) || overlap2(hi, nq * 8, sa, text_len * 4))
+    return fail(RADULS_EINVAL, "lo or hi overlaps an input");
+  std::lock_guard<std::mutex> lock(g_mu);
+  rd::launch_prefix_search(text, text_len, sa, queries, nq, rec_bytes, key_bytes, lo, hi,
+                           (flags & RADULS_SEARCH_NO_NARROWING) ? 0u : 1u, (hipStream_t)stream);
+  HIPCHK(hipGetLastError());
+  return RADULS_OK;
+}
+
+int raduls_sort_search(void* queries, void* tmp, uint64_t nq, uint32_t rec_bytes, uint32_t key_bytes, const void* text,
+                       uint64_t text_len, const uint32_t* sa, uint64_t* lo, uint64_t* hi, void* stream) {
+  int rc = check_shape(rec_bytes, key_bytes);
+  if (rc) return rc;
+  if (nq > 0 && (!text || !sa || !lo || !hi)) return fail(RADULS_EINVAL, "null pointer");
+  if (nq > 0 && (overlap2(lo, nq * 8, tmp, nq * rec_bytes) || overlap2(hi, nq * 8, tmp, nq * rec_bytes)))
+    return fail(RADULS_EINVAL, "lo or hi overlaps tmp");
+  if (nq > 1) {
+    rc = raduls_sort(queries, tmp, nq, rec_bytes, key_bytes, stream);
+    if (rc) return rc;
+  }
+  return raduls_prefix_search(text, text_len, sa, queries, nq, rec_bytes, key_bytes, lo, hi, 0, stream);
+}
+
 int raduls_last_work(uint64_t* host_out, uint32_t count) {
   if (!host_out) return fail(RADULS_EINVAL, "null pointer");
   std::lock_guard<std::mutex> lock(g_mu);

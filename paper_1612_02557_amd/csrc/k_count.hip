@@ -39,9 +39,11 @@ constexpr uint64_t RL_READY = 1ull << 63;
 constexpr uint64_t RL_POISON = 1ull << 62;
 constexpr uint64_t RL_VAL = RL_POISON - 1;
 
+// records per thread of a tile: up to 64 words of records in registers
+__host__ __device__ constexpr uint32_t runs_rows(uint32_t rw) { return rw <= 4 ? 16u : (64u / rw >= 2 ? 64u / rw : 2u); }
 template <int RW>
 constexpr uint32_t runs_per_thread() {
-  return RW <= 2 ? 16u : (32u / RW >= 2 ? 32u / RW : 2u);
+  return runs_rows(RW);
 }
 
 __device__ __forceinline__ uint64_t wave_sum64(uint64_t x) {
@@ -232,8 +234,7 @@ __global__ __launch_bounds__(WG) void k_runs(const uint8_t* src, uint64_t n, Key
 }  // namespace
 
 uint64_t runs_tiles(uint64_t n, uint32_t rec_bytes) {
-  const uint32_t rw = rec_bytes / 4;
-  const uint64_t T = (uint64_t)(rw <= 2 ? 16u : (32u / rw >= 2 ? 32u / rw : 2u)) * WG;
+  const uint64_t T = (uint64_t)runs_rows(rec_bytes / 4) * WG;
   return (n + T - 1) / T;
 }
 

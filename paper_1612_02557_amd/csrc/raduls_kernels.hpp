@@ -31,6 +31,11 @@ uint64_t runs_tiles(uint64_t n, uint32_t rec_bytes);
 void launch_runs(const void* src, uint64_t n, uint32_t rec_bytes, uint32_t key_bytes, void* uniq, uint64_t* counts,
                  uint64_t* num_runs, void* ws, uint32_t spin_limit, hipStream_t s);
 
+// pattern-prefix search over a suffix array (k_search.hip)
+void launch_prefix_search(const void* text, uint64_t N, const uint32_t* sa, const void* queries, uint64_t nq,
+                          uint32_t rec_bytes, uint32_t key_bytes, uint64_t* lo, uint64_t* hi, uint32_t narrow,
+                          hipStream_t s);
+
 // scheduler network
 void launch_mlp_forward(const float* X, const float* theta, float* Y, uint32_t B, hipStream_t s);
 void launch_mlp_loss_grad(const float* X, const float* T, const float* M, const float* theta, float* grad,

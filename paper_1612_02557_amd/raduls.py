@@ -78,6 +78,8 @@ _SIGS = {
     "raduls_partition": (_i32, [_vp, _vp, _u64, _u32, _u32, _u32, _u32, _vp, _vp]),
     "raduls_count_runs": (_i32, [_vp, _u64, _u32, _u32, _vp, _vp, _vp, _vp]),
     "raduls_sort_count": (_i32, [_vp, _vp, _u64, _u32, _u32, _vp, _vp, _vp, _vp]),
+    "raduls_prefix_search": (_i32, [_vp, _u64, _vp, _vp, _u64, _u32, _u32, _vp, _vp, _u32, _vp]),
+    "raduls_sort_search": (_i32, [_vp, _vp, _u64, _u32, _u32, _vp, _u64, _vp, _vp, _vp, _vp]),
     "raduls_sync_check": (_i32, [_vp]),
     "raduls_set_scheduler": (_i32, [_i32, _i32]),
     "raduls_get_scheduler": (_i32, [ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
@@ -298,6 +300,62 @@ def count_runs_ptr(sorted_ptr: int, n: int, rec_bytes: int, key_bytes: int, uniq
                    num_ptr: int, stream: int) -> int:
     """Raw call returning the status code (for argument-error tests)."""
     return lib().raduls_count_runs(sorted_ptr, n, rec_bytes, key_bytes, uniq_ptr, counts_ptr, num_ptr, stream)
+
+
+SEARCH_NO_NARROWING = 1
+
+
+def _search_outputs(nq, device, lo, hi, stream):
+    import torch
+    with torch.cuda.stream(_torch_stream(stream)):
+        if lo is None:
+            lo = torch.empty(nq, dtype=torch.int64, device=device)
+        if hi is None:
+            hi = torch.empty(nq, dtype=torch.int64, device=device)
+    for t in (lo, hi):
+        if not t.is_cuda or t.element_size() != 8 or not t.is_contiguous() or t.numel() < nq:
+            raise ValueError("lo and hi must be contiguous 8-byte CUDA tensors of at least nq entries")
+    return lo, hi
+
+
+def _text_sa(text, sa):
+    import torch
+    if text.dtype != torch.uint8 or text.dim() != 1 or not text.is_contiguous() or not text.is_cuda:
+        raise ValueError("text must be a contiguous 1-D CUDA uint8 tensor")
+    if sa.element_size() != 4 or sa.dim() != 1 or not sa.is_contiguous() or not sa.is_cuda or sa.numel() != text.numel():
+        raise ValueError("sa must be a contiguous 1-D CUDA int32/uint32 tensor of the text's length")
+
+
+def prefix_search(text, sa, queries, key_bytes: int, lo=None, hi=None, narrow: bool = True, stream=None):
+    """Suffix-array range [lo, hi) of each query's key_bytes characters
+    (``raduls_prefix_search``); returns (lo, hi) int64 tensors."""
+    _text_sa(text, sa)
+    q = _records(queries)
+    nq, r = q.shape
+    lo, hi = _search_outputs(nq, q.device, lo, hi, stream)
+    _check(lib().raduls_prefix_search(text.data_ptr(), text.numel(), sa.data_ptr(), q.data_ptr(), nq, r, key_bytes,
+                                      lo.data_ptr(), hi.data_ptr(), 0 if narrow else SEARCH_NO_NARROWING,
+                                      _stream(stream)))
+    return lo[:nq], hi[:nq]
+
+
+def sort_search(text, sa, queries, key_bytes: int, tmp=None, lo=None, hi=None, stream=None):
+    """Sort the query records in place, then search them (``raduls_sort_search``)."""
+    _text_sa(text, sa)
+    q = _records(queries)
+    nq, r = q.shape
+    if tmp is None:
+        tmp = _scratch_like(q, stream)
+    lo, hi = _search_outputs(nq, q.device, lo, hi, stream)
+    _check(lib().raduls_sort_search(q.data_ptr(), tmp.data_ptr(), nq, r, key_bytes, text.data_ptr(), text.numel(),
+                                    sa.data_ptr(), lo.data_ptr(), hi.data_ptr(), _stream(stream)))
+    return lo[:nq], hi[:nq]
+
+
+def prefix_search_ptr(text_ptr, text_len, sa_ptr, q_ptr, nq, rec_bytes, key_bytes, lo_ptr, hi_ptr, flags, stream) -> int:
+    """Raw call returning the status code (for argument-error tests)."""
+    return lib().raduls_prefix_search(text_ptr, text_len, sa_ptr, q_ptr, nq, rec_bytes, key_bytes, lo_ptr, hi_ptr,
+                                      flags, stream)
 
 
 def sync_check(stream=None):

@@ -58,17 +58,27 @@ def exact_index_check(out_dev, inp_dev, rec_bytes: int = 16, key_bytes: int = 8,
         return "unchecked"
     kw = key_bytes // 8
     if rec_bytes == key_bytes:
+        # columns gathered one at a time, `chunk` indices per gather
         o = out_dev.view(torch.int64).view(n, kw)
-        i = inp_dev.view(torch.int64).view(n, kw)
-        perm = torch.sort(_ukey(i[:, 0]), stable=True).indices
+        cols = [inp_dev.view(torch.int64).view(n, kw)[:, w].contiguous() for w in range(kw)]
+
+        def gather(src, idx):
+            out = torch.empty_like(src)
+            for a in range(0, n, chunk):
+                b = min(n, a + chunk)
+                out[a:b] = src[idx[a:b]]
+            return out
+
+        perm = torch.sort(_ukey(cols[0]), stable=True).indices
         if kw == 2:
-            hi = _ukey(i[:, 1])[perm]
-            perm = perm[torch.sort(hi, stable=True).indices]
+            hi = gather(_ukey(cols[1]), perm)
+            perm = gather(perm, torch.sort(hi, stable=True).indices)
             del hi
-        for a in range(0, n, chunk):
-            b = min(n, a + chunk)
-            if not torch.equal(i[perm[a:b]], o[a:b]):
-                return f"output in [{a}, {b}) is not the sorted input"
+        for w in range(kw):
+            for a in range(0, n, chunk):
+                b = min(n, a + chunk)
+                if not torch.equal(cols[w][perm[a:b]], o[a:b, w]):
+                    return f"output in [{a}, {b}) is not the sorted input"
         return None
     if rec_bytes < key_bytes + 8:
         return "unchecked"

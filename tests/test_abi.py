@@ -178,3 +178,20 @@ def test_count_runs_validation(R):
     assert call(p, 1 << 40, 16, 8, p + G, p + 2 * G, p + 3 * G, 0) == R.EUNSUPPORTED
     assert ok_args[0] == p
 
+
+
+def test_prefix_search_validation(R):
+    p = 1 << 20
+    G = 1 << 30
+    call = R.prefix_search_ptr
+    # text, text_len, sa, queries, nq, rec_bytes, key_bytes, lo, hi, flags, stream
+    assert call(p, 100, p + G, p + 2 * G, 10, 6, 4, p + 3 * G, p + 4 * G, 0, 0) == R.EUNSUPPORTED   # rec_bytes % 4
+    assert call(p, 100, p + G, p + 2 * G, 10, 16, 0, p + 3 * G, p + 4 * G, 0, 0) == R.EINVAL        # key_bytes 0
+    assert call(p, 100, p + G, p + 2 * G, 10, 16, 8, p + 3 * G, p + 4 * G, 2, 0) == R.EINVAL        # flags
+    assert call(0, 100, p + G, p + 2 * G, 10, 16, 8, p + 3 * G, p + 4 * G, 0, 0) == R.EINVAL        # null text
+    assert call(p, 0, p + G, p + 2 * G, 10, 16, 8, p + 3 * G, p + 4 * G, 0, 0) == R.EUNSUPPORTED    # empty text
+    assert call(p, 1 << 32, p + G, p + 2 * G, 10, 16, 8, p + 3 * G, p + 4 * G, 0, 0) == R.EUNSUPPORTED
+    assert call(p, 100, p + G, p + 2 * G + 4, 10, 16, 8, p + 3 * G, p + 4 * G, 0, 0) == R.EINVAL    # misaligned queries
+    assert call(p, 100, p + G, p + 2 * G, 10, 16, 8, p + 3 * G, p + 3 * G + 40, 0, 0) == R.EINVAL   # lo and hi overlap
+    assert call(p, 100, p + G, p + 2 * G, 10, 16, 8, p + 2 * G + 64, p + 4 * G, 0, 0) == R.EINVAL   # lo inside queries
+    assert call(0, 0, 0, 0, 0, 16, 8, 0, 0, 0, 0) == R.OK                                           # no queries

@@ -65,12 +65,13 @@ def _keyed(keys, r=16):
 def test_run_structures(R, n, rng):
     """Runs that span many tiles, end exactly on tile boundaries, or are all
     of length one; a single key throughout."""
-    tile = 2048  # records per tile of 16-byte records
+    tile = 4096  # records per tile of 16-byte records
     cases = {
         "all_equal": np.full(n, 42, dtype=np.uint64),
         "all_distinct": np.arange(n, dtype=np.uint64) * np.uint64(977),
         "tile_runs": np.arange(n, dtype=np.uint64) // np.uint64(tile),
         "tile_runs_shifted": (np.arange(n, dtype=np.uint64) + np.uint64(1)) // np.uint64(tile),
+        "half_tile_runs": np.arange(n, dtype=np.uint64) // np.uint64(tile // 2),
         "long_runs": np.sort(rng.integers(0, 7, n, dtype=np.uint64)),
         "pairs": np.arange(n, dtype=np.uint64) // np.uint64(2),
         "zipf": None,
