@@ -17,7 +17,8 @@ the CPU oracle baseline.
 
 Other legs: --batched (many independent arrays in one call vs one call per
 array), --kmer (k-mer counting: sort + duplicate removal with counts, at the
-sizes of the paper's three k-mer sets), --autotune (the autotuner's tuning
+sizes of the paper's three k-mer sets), --search (pattern-prefix search over
+a suffix array, naive vs sorted queries), --autotune (the autotuner's tuning
 for the workload's shape against the defaults).
 """
 from __future__ import annotations
@@ -342,6 +343,155 @@ def kmer_main(args):
     print(json.dumps(out), flush=True)
 
 
+def search_main(args):
+    """Batched pattern-prefix search (paper, Sec. 5): a text of 2^text_log2
+    random DNA characters (two bits of the k-mer generator's genome stream per
+    character), its suffix array (built here by raduls_sort of records keyed
+    by each suffix's first 42 characters, 3 bits each, checked distinct), and
+    2^q_log2 queries of 16 characters (three in four copied from random text
+    positions, one in four random) as 24-byte records (reversed characters,
+    then the query id).  Timed: one full binary search per query in input
+    order (the naive way) against sorting the queries first and searching
+    them in narrowed ranges (raduls_sort_search)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1612_02557_amd import raduls
+    from synth import device as sdev
+    raduls.lib()
+    raduls.set_scheduler(raduls.SCHED_HEURISTIC)
+    raduls.set_timing(0)
+    N, nq, K = 1 << args.text_log2, 1 << args.q_log2, 16
+    log(f"search: text of {N} characters, {nq} queries of {K} characters")
+    words = sdev.generate(synth.Spec(n=(N + 31) // 32, rec_bytes=8, key_bytes=8, dist="uniform", seed=args.seed))
+    w = words.view(torch.int64).view(-1)
+    text = torch.empty(((N + 31) // 32) * 32, dtype=torch.uint8, device="cuda")
+    tv = text.view(-1, 32)
+    for j in range(32):
+        tv[:, j] = (((w >> (2 * j)) & 3) + 1).to(torch.uint8)
+    text = text[:N].contiguous()
+    del words, w, tv
+    # suffix array: 126-bit keys of the first 42 characters (0 past the end)
+    tp = torch.cat([text, torch.zeros(42, dtype=torch.uint8, device="cuda")]).to(torch.int64)
+    lo = torch.zeros(N, dtype=torch.int64, device="cuda")
+    hi = torch.zeros(N, dtype=torch.int64, device="cuda")
+    for j in range(42):
+        c = tp[j:j + N]
+        b = 123 - 3 * j   # lowest bit of character j's field
+        if b >= 64:
+            hi |= c << (b - 64)
+        elif b + 2 < 64:
+            lo |= c << b
+        else:   # the field straddles the words (b = 63): its low bit is lo's top bit
+            lo |= torch.where((c & 1) == 1, torch.iinfo(torch.int64).min, 0)
+            hi |= c >> (64 - b)
+    rec = torch.empty((N, 24), dtype=torch.uint8, device="cuda")
+    rv = rec.view(torch.int64).view(N, 3)
+    rv[:, 0], rv[:, 1] = lo, hi
+    rv[:, 2] = torch.arange(N, dtype=torch.int64, device="cuda")
+    del tp, lo, hi
+    raduls.sort(rec, 16, check=True)
+    rv = rec.view(torch.int64).view(N, 3)
+    ulo, uhi = rv[:, 0] ^ torch.iinfo(torch.int64).min, rv[:, 1] ^ torch.iinfo(torch.int64).min
+    distinct = bool(((uhi[1:] > uhi[:-1]) | ((uhi[1:] == uhi[:-1]) & (ulo[1:] > ulo[:-1]))).all().item())
+    sa = rv[:, 2].to(torch.int32).contiguous()
+    del rec, rv, ulo, uhi
+    torch.cuda.empty_cache()
+    # queries
+    g = torch.Generator(device="cuda")
+    g.manual_seed(args.seed)
+    pos = torch.randint(0, N - K, (nq,), device="cuda", generator=g)
+    qchars = text[pos.unsqueeze(1) + torch.arange(K, device="cuda")]
+    rnd = torch.randint(1, 5, (nq, K), device="cuda", generator=g, dtype=torch.int64).to(torch.uint8)
+    take = (torch.arange(nq, device="cuda") % 4 == 3).unsqueeze(1)
+    qchars = torch.where(take, rnd, qchars)
+    pristine = torch.zeros((nq, 24), dtype=torch.uint8, device="cuda")
+    pristine[:, :K] = qchars.flip(1)
+    pristine.view(torch.int64).view(nq, 3)[:, 2] = torch.arange(nq, dtype=torch.int64, device="cuda")
+    del qchars, rnd, take, pos
+    q = torch.empty_like(pristine)
+    tmp = torch.empty_like(pristine)
+    lo1 = torch.empty(nq, dtype=torch.int64, device="cuda")
+    hi1 = torch.empty_like(lo1)
+    lo2 = torch.empty_like(lo1)
+    hi2 = torch.empty_like(lo1)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+    def timed(fn):
+        q.copy_(pristine)
+        torch.cuda.synchronize()
+        ev[0].record()
+        fn()
+        ev[1].record()
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1])
+
+    def naive():
+        raduls.prefix_search(text, sa, q, K, lo=lo1, hi=hi1, narrow=False)
+
+    def sorted_search():
+        raduls.sort_search(text, sa, q, K, tmp=tmp, lo=lo2, hi=hi2)
+
+    for _ in range(args.warmup):
+        timed(naive)
+        timed(sorted_search)
+    tn = [timed(naive) for _ in range(args.steps)]
+    ts = [timed(sorted_search) for _ in range(args.steps)]
+    # the search alone on the sorted queries now in q
+    t_alone = []
+    for _ in range(args.steps):
+        ev[0].record()
+        raduls.prefix_search(text, sa, q, K, lo=lo2, hi=hi2)
+        ev[1].record()
+        torch.cuda.synchronize()
+        t_alone.append(ev[0].elapsed_time(ev[1]))
+    raduls.sync_check()
+    # checks: both ways give the same range for every query (through the ids);
+    # sampled ranges bound the matching suffixes (text gathers on the device)
+    ids = q.view(torch.int64).view(nq, 3)[:, 2]
+    same = bool(torch.equal(lo1[ids], lo2) and torch.equal(hi1[ids], hi2))
+    smp = torch.randint(0, nq, (4096,), device="cuda", generator=g)
+    qk = pristine[smp, :K].flip(1).to(torch.int64)             # characters in reading order
+
+    def pref(rank):
+        p = sa[rank.clamp(0, N - 1)].to(torch.int64)
+        idx = p.unsqueeze(1) + torch.arange(K, device="cuda")
+        c = text[idx.clamp(max=N - 1)].to(torch.int64)
+        return torch.where(idx < N, c, torch.zeros_like(c))
+
+    def cmp(a, b):   # -1, 0, 1 per row, first differing character decides
+        d = torch.sign(a - b)
+        first = torch.argmax((d != 0).to(torch.int8), dim=1)
+        return d.gather(1, first.unsqueeze(1)).squeeze(1)
+
+    l_, h_ = lo1[smp], hi1[smp]
+    ok = bool((l_ <= h_).all().item())
+    ok &= bool(((l_ == 0) | (cmp(pref(l_ - 1), qk) < 0)).all().item())
+    ok &= bool(((l_ == N) | (cmp(pref(l_), qk) >= 0)).all().item())
+    ok &= bool(((h_ == l_) | (cmp(pref(h_ - 1), qk) == 0)).all().item())
+    ok &= bool(((h_ == N) | (cmp(pref(h_), qk) > 0)).all().item())
+    found = int((hi1 > lo1).sum().item())
+    mn, ms, ma = statistics.median(tn), statistics.median(ts), statistics.median(t_alone)
+    io_bytes = nq * (24 + 16)
+    out = {"metric": "patterns searched per second in a suffix array (sort + narrowed search), 16-character prefixes",
+           "value": nq / (ms / 1e3), "unit": "queries/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u128",
+           "data": "synthetic",
+           "config": {"workload": f"{nq} queries of 16 characters (3/4 taken from the text, 1/4 random) against the "
+                                  f"suffix array of 2^{args.text_log2} random DNA characters", "text": N,
+                      "queries": nq, "seed": args.seed},
+           "roofline": {"bound": "latency", "kernel": "k_prefix_search", "achieved": io_bytes / ma / 1e6,
+                        "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": io_bytes / ma / 1e6 / HBM_PEAK_GBPS,
+                        "traffic": None, "alg_bytes_per_launch": io_bytes, "avg_launch_ms": ma,
+                        "note": "dependent random probes; the bytes are the queries read and the ranges written"},
+           "naive_ms": mn, "naive_value": nq / (mn / 1e3), "sorted_over_naive": mn / ms, "search_alone_ms": ma,
+           "queries_found": found, "suffixes_distinct": distinct, "verified": bool(same and ok and distinct),
+           "step_ms": ts, "naive_step_ms": tn}
+    log(f"search: naive {mn:.2f} ms, sort + search {ms:.2f} ms (search alone {ma:.2f} ms), {found} queries found")
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -364,6 +514,9 @@ def main():
     ap.add_argument("--seg-hi", type=int, default=1 << 22)
     ap.add_argument("--kmer", action="store_true", help="k-mer counting: sort + duplicate removal with counts")
     ap.add_argument("--kmer-sizes", default="63000000,413000000,1887000000")
+    ap.add_argument("--search", action="store_true", help="batched pattern-prefix search over a suffix array")
+    ap.add_argument("--text-log2", type=int, default=28)
+    ap.add_argument("--q-log2", type=int, default=24)
     ap.add_argument("--autotune", action="store_true",
                     help="time the autotuner's tuning for this shape against the defaults")
     args = ap.parse_args()
@@ -377,6 +530,8 @@ def main():
         return batched_main(args)
     if args.kmer:
         return kmer_main(args)
+    if args.search:
+        return search_main(args)
 
     import torch
 
