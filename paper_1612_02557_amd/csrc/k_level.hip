@@ -292,14 +292,18 @@ __global__ __launch_bounds__(WG) void k_hist(Plan p, Work w, uint32_t level, con
 // them out as the tile's counts and adds them to per-lane totals, which go to
 // the bucket's histogram (and the key-bit OR to its varying mask) when the
 // wave moves on to another bucket.  No workgroup barrier, so a wave's loads
-// keep streaming from one tile into the next.
-template <int RW>
+// keep streaming from one tile into the next: each wave has two sets of
+// counters, and a tile's counts are read out only once the first keys of
+// the wave's next tile have been requested (into the other set), so the
+// read-out overlaps those loads.
+template <int RW, bool WIDE>
 __global__ __launch_bounds__(WG) void k_hist_wave(Plan p, Work w, uint32_t level, const uint8_t* rec0,
                                                   const uint8_t* rec1) {
   constexpr uint32_t RMAX = 256;
-  constexpr uint32_t HB = 16;          // keys loaded per lane before they are counted
+  constexpr uint32_t HB = 8;           // keys loaded per lane before they are counted
   constexpr uint32_t DL = RMAX / 64;   // digits per lane
-  __shared__ uint32_t sh[NWAVES * RMAX];
+  constexpr uint32_t RB = RW * 4;      // record bytes
+  __shared__ uint32_t sh[2 * NWAVES * RMAX];
   const Bucket* list = level_list(p, w, level);
   const uint64_t* start = level_start(p, w, level);
   const uint32_t nb = min((uint64_t)w.ctl->nbig[level], p.cap_big);
@@ -312,8 +316,8 @@ __global__ __launch_bounds__(WG) void k_hist_wave(Plan p, Work w, uint32_t level
   const uint32_t wave = threadIdx.x / 64;
   const uint32_t RS = 1u << p.d_big;
   const uint32_t IPW = p.tile / 64;    // records per lane of a tile
-  uint32_t* cw = sh + wave * RMAX;
-  for (uint32_t v = threadIdx.x; v < NWAVES * RMAX; v += WG) sh[v] = 0;
+  uint32_t* const cset0 = sh + wave * 2 * RMAX;
+  for (uint32_t v = threadIdx.x; v < 2 * NWAVES * RMAX; v += WG) sh[v] = 0;
   __syncthreads();
   constexpr uint32_t NONE = 0xFFFFFFFFu;
   uint32_t b = NONE, d = 0, shift = 0, mask = 0;
@@ -322,6 +326,8 @@ __global__ __launch_bounds__(WG) void k_hist_wave(Plan p, Work w, uint32_t level
   Key ref{0, 0};
   uint64_t vlo = 0, vhi = 0;
   uint32_t acc[DL];
+#pragma unroll
+  for (uint32_t k = 0; k < DL; k++) acc[k] = 0;
   auto flush = [&]() {
     uint64_t* gh = w.hist + (uint64_t)b * RS;
 #pragma unroll
@@ -335,37 +341,82 @@ __global__ __launch_bounds__(WG) void k_hist_wave(Plan p, Work w, uint32_t level
       if (c) atomicOr((unsigned long long*)&w.vary[2 * b + 1], (unsigned long long)c);
     }
   };
+  // read out (and clear) the counters of tile tt, digit width dd
+  auto readout = [&](uint32_t* cw, uint64_t tt, uint32_t dd) {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    uint32_t* tc = w.tcnt + tt * RS;
+#pragma unroll
+    for (uint32_t k = 0; k < DL; k++) {
+      const uint32_t v = lane + 64 * k;
+      if (v < (1u << dd)) {
+        const uint32_t c = cw[v];
+        cw[v] = 0;
+        tc[v] = c;
+        acc[k] += c;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  };
+  uint32_t cur = 0;            // counter set of the current tile
+  bool pending = false;        // the previous tile's counts are still in the other set
+  uint64_t tprev = 0;
+  uint32_t dprev = 0;
   for (uint64_t t = ta + wave; t < tz; t += NWAVES) {
-    if (b == NONE || t >= bnext) {
+    // the tile's bucket (the wave's tiles are increasing, so it only moves on)
+    const bool nextb = b == NONE || t >= bnext;
+    uint32_t nbk = b;
+    if (nextb) {
+      if (b == NONE) nbk = find_entry(start, nb, t);
+      else while (start[nbk + 1] <= t) nbk++;
+    }
+    const Bucket B = list[nbk];
+    const uint64_t nbt0 = start[nbk];
+    const uint64_t nbegin = B.begin, nend = B.begin + B.count;
+    const uint32_t nd = min(p.d_big, kf.kbits - B.bit);
+    const uint32_t nshift = kf.kbits - B.bit - nd;
+    const uint8_t* nsrc = (B.flags & BF_TMP) ? rec1 : rec0;
+    const uint64_t r0 = nbegin + (t - nbt0) * p.tile;
+    // the tile's records through a buffer resource: one offset register per
+    // lane, and records past the tile's end read as 0 (they are not counted)
+    const uint32_t cnt = (uint32_t)min((uint64_t)p.tile, nend - r0);
+    const __amdgpu_buffer_rsrc_t rs = job_rsrc(nsrc + r0 * RB, cnt * RB);
+    const uint32_t voff = lane * RB;
+    // the first keys of this tile are requested before the previous tile's
+    // counts are read out
+    Key kk[HB];
+    Key nref = ref;
+    if (nextb) nref = load_key<RW>(nsrc, nbegin, kf);
+#pragma unroll
+    for (uint32_t u = 0; u < HB; u++) kk[u] = buf_load_key<RW, WIDE>(rs, voff, u * 64 * RB, kf);
+    if (pending) readout(cset0 + (cur ^ 1u) * RMAX, tprev, dprev);
+    if (nextb) {
       if (b != NONE) flush();
-      if (b == NONE) b = find_entry(start, nb, t);
-      else while (start[b + 1] <= t) b++;
-      const Bucket B = list[b];
-      bt0 = start[b];
+      b = nbk;
+      bt0 = nbt0;
       bnext = start[b + 1];
-      bbegin = B.begin;
-      bend = B.begin + B.count;
-      d = min(p.d_big, kf.kbits - B.bit);
-      shift = kf.kbits - B.bit - d;
+      bbegin = nbegin;
+      bend = nend;
+      d = nd;
+      shift = nshift;
       mask = (1u << d) - 1u;
-      src = (B.flags & BF_TMP) ? rec1 : rec0;
-      ref = load_key<RW>(src, B.begin, kf);
+      src = nsrc;
+      ref = nref;
       vlo = vhi = 0;
 #pragma unroll
       for (uint32_t k = 0; k < DL; k++) acc[k] = 0;
     }
-    const uint64_t r0 = bbegin + (t - bt0) * p.tile;
+    uint32_t* cw = cset0 + cur * RMAX;
     for (uint32_t j0 = 0; j0 < IPW; j0 += HB) {
-      Key kk[HB];
+      if (j0 > 0) {
 #pragma unroll
-      for (uint32_t u = 0; u < HB; u++) {
-        const uint64_t i = r0 + (uint64_t)(j0 + u) * 64 + lane;
-        kk[u] = (j0 + u < IPW && i < bend) ? load_key<RW>(src, i, kf) : ref;
+        for (uint32_t u = 0; u < HB; u++) kk[u] = buf_load_key<RW, WIDE>(rs, voff, (j0 + u) * 64 * RB, kf);
       }
 #pragma unroll
       for (uint32_t u = 0; u < HB; u++) {
-        const uint64_t i = r0 + (uint64_t)(j0 + u) * 64 + lane;
-        const bool valid = j0 + u < IPW && i < bend;
+        const bool valid = j0 + u < IPW && (j0 + u) * 64 + lane < cnt;
+        if (!valid) kk[u] = ref;
         vlo |= kk[u].lo ^ ref.lo;
         vhi |= kk[u].hi ^ ref.hi;
         const uint32_t v = key_digit(kk[u], shift, mask, kf);
@@ -378,22 +429,12 @@ __global__ __launch_bounds__(WG) void k_hist_wave(Plan p, Work w, uint32_t level
         }
       }
     }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    uint32_t* tc = w.tcnt + t * RS;
-#pragma unroll
-    for (uint32_t k = 0; k < DL; k++) {
-      const uint32_t v = lane + 64 * k;
-      if (v < (1u << d)) {
-        const uint32_t c = cw[v];
-        cw[v] = 0;
-        tc[v] = c;
-        acc[k] += c;
-      }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
+    pending = true;
+    tprev = t;
+    dprev = d;
+    cur ^= 1u;
   }
+  if (pending) readout(cset0 + (cur ^ 1u) * RMAX, tprev, dprev);
   if (b != NONE) flush();
 }
 
@@ -979,7 +1020,10 @@ void launch_level_hist(const Plan& p, const Work& w, uint32_t level, void* recor
   const uint8_t* r1 = (const uint8_t*)tmp;
   switch (p.rw * 2 + (p.d_big > 8 ? 1 : 0)) {
 #define RD_CASE(n)                                                                         \
-  case 2 * n: k_hist_wave<n><<<p.grid_hist, WG, 0, s>>>(p, w, level, r0, r1); break;     \
+  case 2 * n:                                                                              \
+    if (p.key_bytes > 8) k_hist_wave<n, true><<<p.grid_hist, WG, 0, s>>>(p, w, level, r0, r1); \
+    else k_hist_wave<n, false><<<p.grid_hist, WG, 0, s>>>(p, w, level, r0, r1);            \
+    break;                                                                                 \
   case 2 * n + 1: k_hist<n, 11><<<p.grid_hist, WG, 0, s>>>(p, w, level, r0, r1); break;
     RD_CASE(1) RD_CASE(2) RD_CASE(3) RD_CASE(4) RD_CASE(5) RD_CASE(6) RD_CASE(7) RD_CASE(8)
     RD_CASE(9) RD_CASE(10) RD_CASE(11) RD_CASE(12) RD_CASE(13) RD_CASE(14) RD_CASE(15) RD_CASE(16)

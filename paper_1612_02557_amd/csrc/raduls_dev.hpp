@@ -232,6 +232,33 @@ __device__ __forceinline__ Key load_key(const uint8_t* __restrict__ base, uint64
   return Key{lo & f.mlo, hi & f.mhi};
 }
 
+// The key of a record through a buffer resource (record at voff + soff);
+// WIDE: keys may be longer than 8 bytes (else the high word is not loaded).
+template <int RW, bool WIDE = true>
+__device__ __forceinline__ Key buf_load_key(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff, const KeyFmt& f) {
+  uint64_t lo = 0, hi = 0;
+  if constexpr (RW % 2 == 0) {
+    const v2u a = __builtin_bit_cast(v2u, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)voff, (int)soff, 0));
+    lo = a.x | ((uint64_t)a.y << 32);
+    if constexpr (RW >= 4 && WIDE) {
+      if (f.mhi) {
+        const v2u b = __builtin_bit_cast(v2u, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)voff + 8, (int)soff, 0));
+        hi = b.x | ((uint64_t)b.y << 32);
+      }
+    }
+  } else {
+    lo = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)voff, (int)soff, 0);
+    if constexpr (RW > 1) lo |= (uint64_t)__builtin_amdgcn_raw_buffer_load_b32(rs, (int)voff + 4, (int)soff, 0) << 32;
+    if constexpr (RW > 2 && WIDE) {
+      if (f.mhi) hi = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)voff + 8, (int)soff, 0);
+    }
+    if constexpr (RW > 3 && WIDE) {
+      if (f.mhi) hi |= (uint64_t)__builtin_amdgcn_raw_buffer_load_b32(rs, (int)voff + 12, (int)soff, 0) << 32;
+    }
+  }
+  return Key{lo & f.mlo, WIDE ? (hi & f.mhi) : 0ull};
+}
+
 __device__ __forceinline__ uint64_t shr128_lo(Key k, uint32_t s) {
   if (s >= 64) return k.hi >> (s - 64);
   if (s == 0) return k.lo;
