@@ -833,23 +833,22 @@ __global__ __launch_bounds__(WG) void k_scatter(Plan p, Work w, uint32_t level, 
     uint32_t mask = R - 1u;
     uint8_t* dst = (B.flags & BF_TMP) ? rec0w : rec1w;
 
-    uint32_t dg[IPT_MAX];
+    // one register of rank state per record (the digit is recomputed from
+    // the record where it is needed): more waves fit the register file
     uint32_t rk[IPT_MAX];
     uint64_t wbase = r0 + (uint64_t)wave * per_wave;
-    RankPart rp[IPT_MAX];
 #pragma unroll
     for (uint32_t j = 0; j < IPT_MAX; j++) {
       if (j < IPT) {
         uint64_t i = wbase + (uint64_t)j * 64 + lane;
         bool valid = i < bend;
         uint32_t v = valid ? key_digit(rec_key<RW>(rec[j], kf), shift, mask, kf) : 0u;
-        rp[j] = rank_issue(&wcnt[wave * RMAX], v, d, valid);
-        dg[j] = v;
+        rk[j] = rank_issue32(&wcnt[wave * RMAX], v, d, valid);
       }
     }
 #pragma unroll
     for (uint32_t j = 0; j < IPT_MAX; j++)
-      if (j < IPT) rk[j] = rank_finish(rp[j]);
+      if (j < IPT) rk[j] = rank_finish32(rk[j]);
     __syncthreads();
     // the tile's digit counts: per-wave bases, and the tile's own digit
     // starts (an exclusive scan) for staging
@@ -867,7 +866,8 @@ __global__ __launch_bounds__(WG) void k_scatter(Plan p, Work w, uint32_t level, 
       if (j < IPT) {
         uint64_t i = wbase + (uint64_t)j * 64 + lane;
         if (i < bend) {
-          uint32_t pos = toff[dg[j]] + wcnt[wave * RMAX + dg[j]] + rk[j];
+          const uint32_t v = key_digit(rec_key<RW>(rec[j], kf), shift, mask, kf);
+          uint32_t pos = toff[v] + wcnt[wave * RMAX + v] + rk[j];
           lds_put<RW>(stage, pos, rec[j]);
         }
       }

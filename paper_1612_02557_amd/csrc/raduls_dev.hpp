@@ -345,6 +345,25 @@ __device__ __forceinline__ uint32_t rank_finish(RankPart r) {
   return base + (r.info & 0xFFFFu);
 }
 
+// The same with the round's state in one register: the counter's old value
+// (valid in the leader lane, below 2^16) | peers below this lane << 16 |
+// leader lane << 24.
+__device__ __forceinline__ uint32_t rank_issue32(uint32_t* wc, uint32_t v, uint32_t d, bool valid) {
+  const uint64_t active = __ballot(valid);
+  const uint64_t peers = match_digit(v, d, active);
+  const uint32_t lane = __lane_id();
+  const uint32_t leader = valid ? (uint32_t)(__ffsll((long long)peers) - 1) : lane;
+  uint32_t old = 0;
+  if (valid && leader == lane) old = atomicAdd(&wc[v], (uint32_t)__popcll(peers));
+  const uint64_t below = lane == 0 ? 0ull : (peers & (~0ull >> (64 - lane)));
+  return old | ((uint32_t)__popcll(below) << 16) | (leader << 24);
+}
+
+__device__ __forceinline__ uint32_t rank_finish32(uint32_t x) {
+  const uint32_t base = (uint32_t)__shfl((int)x, (int)(x >> 24)) & 0xFFFFu;
+  return base + ((x >> 16) & 0xFFu);
+}
+
 __device__ __forceinline__ uint64_t wave_or64(uint64_t x) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) x |= __shfl_xor(x, o);
