@@ -268,6 +268,12 @@ def kmer_main(args):
     raduls.set_scheduler(raduls.SCHED_HEURISTIC)
     raduls.set_timing(0)
     sizes = [int(x) for x in args.kmer_sizes.split(",")]
+    if args.autotune:
+        t0 = time.perf_counter()
+        for n in sizes:
+            raduls.tune(16, 16, n)
+        log(f"k-mers: autotuned in {time.perf_counter() - t0:.1f} s: "
+            f"{[raduls.effective_tuning(16, 16, n).as_dict() for n in sizes]}")
     legs = []
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     for n in sizes:
@@ -339,7 +345,8 @@ def kmer_main(args):
            "roofline": {"bound": "hbm", "kernel": "k_runs", "achieved": big["count_runs_GBps"],
                         "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": big["count_runs_frac"], "traffic": None,
                         "alg_bytes_per_launch": big["count_runs_alg_bytes"], "avg_launch_ms": big["ms_count_runs"]},
-           "legs": legs, "verified": all(l_["verified"] for l_ in legs)}
+           "legs": legs, "verified": all(l_["verified"] for l_ in legs),
+           "tuning": ([raduls.effective_tuning(16, 16, n).as_dict() for n in sizes] if args.autotune else "default")}
     print(json.dumps(out), flush=True)
 
 
