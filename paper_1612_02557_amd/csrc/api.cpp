@@ -217,16 +217,16 @@ Plan make_plan(uint64_t n, uint32_t r, uint32_t k, const raduls_tuning& t, int c
   p.grid_clear = cus * 4;
   uint64_t W = p.grid_small;
   p.t_big = std::max<uint64_t>(t.big_min, (uint64_t)p.c_fin);
-  // Register finishing (keys of at most 8 bytes; not while a procedure is
-  // forced or traced, which concern the LDS procedures): a 1024-thread
-  // workgroup finishes jobs of up to fin_max records, so buckets up to that
-  // size leave the levels.
+  // Register finishing (not while a procedure is forced or traced, which
+  // concern the LDS procedures): a 1024-thread workgroup finishes jobs of up
+  // to fin_max records (half as many for keys above 8 bytes, whose
+  // composites take 128 bits), so buckets up to that size leave the levels.
   p.fin_max = 0;
   p.grid_fin = cus;
   const int lds_limit = device_lds_per_block();
-  if (allow_fin && t.reg_finish && k <= 8 && g_sched_mode != RADULS_SCHED_FORCED &&
+  if (allow_fin && t.reg_finish && g_sched_mode != RADULS_SCHED_FORCED &&
       (lds_limit <= 0 || lds_limit >= (int)(rd::FIN_LDS_BYTES + rd::FIN_STATIC_LDS))) {
-    p.fin_max = rd::fin_records_per_thread(p.rw) * rd::FIN_THREADS;
+    p.fin_max = (k > 8 ? rd::fin_records_per_thread_wide(p.rw) : rd::fin_records_per_thread(p.rw)) * rd::FIN_THREADS;
     p.t_big = std::max<uint64_t>(t.big_min, (uint64_t)p.fin_max);
     const uint32_t fjob = t.job_records ? std::min<uint32_t>(std::max<uint32_t>(t.job_records, p.c_fin), p.fin_max)
                                         : p.fin_max;
@@ -238,12 +238,12 @@ Plan make_plan(uint64_t n, uint32_t r, uint32_t k, const raduls_tuning& t, int c
   p.cap_big = n / (p.t_big + 1) + 2;
   if (p.fin_max) {
     // With register finishing a bucket also takes a level when its
-    // composite would not fit 64 bits, which depends on its resolved bits:
+    // composite would not fit, which depends on its resolved bits:
     // a bucket below a level has at least d_big of them (the root and the
     // segments have none).
     const uint32_t kb = 8 * k, b1 = std::min<uint32_t>(p.d_big, kb);
     const uint32_t below = kb - b1 > rd::FIN_DIGIT_BITS ? kb - b1 - rd::FIN_DIGIT_BITS : 0;
-    const uint32_t ibmax = 64 - below;
+    const uint32_t ibmax = rd::fin_comp_bits(kb) - below;
     const uint64_t cap1 = ibmax >= 32 ? p.fin_max : std::min<uint64_t>(p.fin_max, 1ull << ibmax);
     p.cap_big = n / (std::min<uint64_t>(p.t_big, cap1) + 1) + 2 + std::min<uint64_t>(segs, n / 33 + 1);
   }

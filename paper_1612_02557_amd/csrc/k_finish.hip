@@ -23,13 +23,72 @@
 //
 // Composites are unique (they hold the index), so every step's result is
 // the stable order whatever order the atomics gave.  A job qualifies when
-// its key bits below the digit plus the index bits fit 64 bits (the levels
-// route only such jobs here).  Jobs whose keys are all equal are written
-// unchanged.
+// its key bits below the digit plus the index bits fit the composite (the
+// levels route only such jobs here): 64 bits for keys of at most 8 bytes,
+// 128 bits for longer keys, whose jobs hold half as many records (the
+// composites of a job fill the same LDS).  Jobs whose keys are all equal are
+// written unchanged.
+#include <type_traits>
+
 #include "raduls_dev.hpp"
 #include "raduls_kernels.hpp"
 
 namespace rd {
+
+// 128-bit keys and composites of jobs with keys above 8 bytes.
+struct FU128 {
+  uint64_t lo, hi;
+};
+__device__ __forceinline__ FU128 operator^(FU128 a, FU128 b) { return FU128{a.lo ^ b.lo, a.hi ^ b.hi}; }
+__device__ __forceinline__ FU128 operator|(FU128 a, FU128 b) { return FU128{a.lo | b.lo, a.hi | b.hi}; }
+__device__ __forceinline__ FU128 operator&(FU128 a, FU128 b) { return FU128{a.lo & b.lo, a.hi & b.hi}; }
+__device__ __forceinline__ FU128 operator|(FU128 a, uint32_t q) { return FU128{a.lo | q, a.hi}; }
+__device__ __forceinline__ FU128 operator>>(FU128 a, uint32_t s) {
+  if (s == 0) return a;
+  if (s >= 64) return FU128{s >= 128 ? 0ull : a.hi >> (s - 64), 0ull};
+  return FU128{(a.lo >> s) | (a.hi << (64 - s)), a.hi >> s};
+}
+__device__ __forceinline__ FU128 operator<<(FU128 a, uint32_t s) {
+  if (s == 0) return a;
+  if (s >= 64) return FU128{0ull, s >= 128 ? 0ull : a.lo << (s - 64)};
+  return FU128{a.lo << s, (a.hi << s) | (a.lo >> (64 - s))};
+}
+__device__ __forceinline__ bool operator<(FU128 a, FU128 b) { return a.hi < b.hi || (a.hi == b.hi && a.lo < b.lo); }
+__device__ __forceinline__ bool operator>(FU128 a, FU128 b) { return b < a; }
+__device__ __forceinline__ bool operator==(FU128 a, FU128 b) { return a.lo == b.lo && a.hi == b.hi; }
+__device__ __forceinline__ bool operator!=(FU128 a, FU128 b) { return !(a == b); }
+
+// the same operations on both key types
+__device__ __forceinline__ uint32_t low32(uint64_t x) { return (uint32_t)x; }
+__device__ __forceinline__ uint32_t low32(FU128 x) { return (uint32_t)x.lo; }
+__device__ __forceinline__ bool is_zero(uint64_t x) { return x == 0; }
+__device__ __forceinline__ bool is_zero(FU128 x) { return (x.lo | x.hi) == 0; }
+__device__ __forceinline__ uint32_t lowest_bit(uint64_t x) { return (uint32_t)__builtin_ctzll(x); }
+__device__ __forceinline__ uint32_t lowest_bit(FU128 x) {
+  return x.lo ? (uint32_t)__builtin_ctzll(x.lo) : 64u + (uint32_t)__builtin_ctzll(x.hi);
+}
+__device__ __forceinline__ uint32_t bit_length(uint64_t x) { return 64u - (uint32_t)__clzll(x); }
+__device__ __forceinline__ uint32_t bit_length(FU128 x) {
+  return x.hi ? 128u - (uint32_t)__clzll(x.hi) : 64u - (uint32_t)__clzll(x.lo);
+}
+template <typename K>
+__device__ __forceinline__ K zero_key() {
+  if constexpr (std::is_same<K, FU128>::value) return FU128{0ull, 0ull};
+  else return 0ull;
+}
+// bits [0, rb) set
+template <typename K>
+__device__ __forceinline__ K low_mask(uint32_t rb) {
+  if constexpr (std::is_same<K, FU128>::value) {
+    if (rb == 0) return FU128{0ull, 0ull};
+    if (rb < 64) return FU128{(1ull << rb) - 1, 0ull};
+    return FU128{~0ull, rb >= 128 ? ~0ull : (rb == 64 ? 0ull : ((1ull << (rb - 64)) - 1))};
+  } else {
+    return rb == 0 ? 0ull : (rb >= 64 ? ~0ull : ((1ull << rb) - 1));
+  }
+}
+__device__ __forceinline__ uint64_t uniform_key(uint64_t x) { return uniform64(x); }
+__device__ __forceinline__ FU128 uniform_key(FU128 x) { return FU128{uniform64(x.lo), uniform64(x.hi)}; }
 
 constexpr int FWG = 1024;              // threads of a finishing workgroup
 constexpr int FWAVES = FWG / 64;
@@ -37,16 +96,19 @@ constexpr uint32_t FSUB = 32;          // larger sub-bins are split or sorted by
 constexpr uint32_t FIN_SPLIT_MAX = 64; // large sub-bins that may be split
 constexpr uint32_t FIN_MINORS = 24;    // records of a split sub-bin outside its run of equal keys
 constexpr uint32_t FIN_POOL_WAVE = 32; // pool of those records' composites, per wave
-constexpr uint32_t FIN_POOL = FIN_POOL_WAVE * FWAVES;
 
-template <int RW>
+template <int RW, bool WIDE>
 struct FinShape {
-  static constexpr uint32_t E = fin_records_per_thread(RW);
+  static constexpr uint32_t E = WIDE ? fin_records_per_thread_wide(RW) : fin_records_per_thread(RW);
   static constexpr uint32_t M = E * FWG;
 };
 
+// K: the key and composite type (64-bit, or 128-bit for keys above 8 bytes,
+// which keep half the pool so that the static LDS stays the same)
+template <typename K>
 struct FinShared {
-  uint64_t wv[FWAVES];                 // per-wave OR of key XOR reference
+  static constexpr uint32_t POOL_WAVE = sizeof(K) == 8 ? FIN_POOL_WAVE : FIN_POOL_WAVE / 2;
+  K wv[FWAVES];                        // per-wave OR of key XOR reference
   uint32_t wsum[FWAVES];               // per-wave sums of the counter scan
   uint32_t wmax[FWAVES];
   uint32_t job[2];                     // claimed job index (by iteration parity)
@@ -56,17 +118,18 @@ struct FinShared {
   uint8_t rank8[256];                  // grouped job: rank of a top-8-bit value among those present
   uint8_t btag[1u << FIN_DIGIT_BITS];  // sub-bin -> 1 + its index among the split ones, or 0
   // split large sub-bins (the first FIN_SPLIT_MAX of them in digit order)
-  uint64_t bH[FIN_SPLIT_MAX];          // the shared key part
+  K bH[FIN_SPLIT_MAX];                 // the shared key part
   uint32_t binfo[FIN_SPLIT_MAX];       // pool offset | minors << 16
   uint32_t bless[FIN_SPLIT_MAX];       // minors with a smaller key part
   union {
     uint32_t h8[256];                  // grouped job: counts of the top 8 varying bits
     uint32_t cw[FWAVES * FIN_SPLIT_MAX];  // H records per wave, then those of earlier waves
   };
-  uint64_t pool[FIN_POOL];             // the minors' composites
+  K pool[POOL_WAVE * FWAVES];          // the minors' composites
 };
 
-static_assert(sizeof(FinShared) <= FIN_STATIC_LDS, "static LDS of the finishing kernel");
+static_assert(sizeof(FinShared<uint64_t>) <= FIN_STATIC_LDS, "static LDS of the finishing kernel");
+static_assert(sizeof(FinShared<FU128>) <= FIN_STATIC_LDS, "static LDS of the finishing kernel");
 
 // Keeps the scheduler from interleaving the unrolled per-record iterations
 // (that would hold every iteration's temporaries at once and spill).
@@ -85,6 +148,9 @@ __device__ __forceinline__ uint64_t fwave_or64(uint64_t x, uint32_t lane) {
     x |= (uint64_t)lo | ((uint64_t)hi << 32);
   }
   return x;
+}
+__device__ __forceinline__ FU128 fwave_or64(FU128 x, uint32_t lane) {
+  return FU128{fwave_or64(x.lo, lane), fwave_or64(x.hi, lane)};
 }
 __device__ __forceinline__ uint32_t fwave_max(uint32_t x, uint32_t lane) {
 #pragma unroll
@@ -112,6 +178,19 @@ __device__ __forceinline__ uint64_t fkey(const Rec<RW>& r, uint64_t km) {
   uint64_t k = r.w[0];
   if constexpr (RW > 1) k |= (uint64_t)r.w[1] << 32;
   return k & km;
+}
+// the key as K: 64 bits (masks lo) or 128 bits (masks lo, hi)
+template <typename K, int RW>
+__device__ __forceinline__ K fkey_k(const Rec<RW>& r, uint64_t km, uint64_t kmh) {
+  if constexpr (std::is_same<K, FU128>::value) {
+    uint64_t h = 0;
+    if constexpr (RW > 2) h = r.w[2];
+    if constexpr (RW > 3) h |= (uint64_t)r.w[3] << 32;
+    return FU128{fkey<RW>(r, km), h & kmh};
+  } else {
+    (void)kmh;
+    return fkey<RW>(r, km);
+  }
 }
 __device__ __forceinline__ uint64_t phase_mask(uint64_t km) {
   asm volatile("" : "+s"(km));
@@ -154,17 +233,20 @@ __device__ __forceinline__ void wave_bitonic(T* c, uint32_t s, uint32_t lane) {
   }
 }
 
-template <int RW>
+template <int RW, bool WIDE>
 __global__ __launch_bounds__(FWG) void k_fin_jobs(Plan p, Work w, uint8_t* rec0, uint8_t* rec1) {
-  constexpr uint32_t E = FinShape<RW>::E;
-  constexpr uint32_t M = FinShape<RW>::M;
+  using K = typename std::conditional<WIDE, FU128, uint64_t>::type;  // keys and composites
+  constexpr uint32_t E = FinShape<RW, WIDE>::E;
+  constexpr uint32_t M = FinShape<RW, WIDE>::M;
+  constexpr uint32_t CB = 8 * sizeof(K);   // composite bits
+  constexpr uint32_t POOL_WAVE = FinShared<K>::POOL_WAVE;
   constexpr uint32_t RMAX = 1u << FIN_DIGIT_BITS;
   constexpr uint32_t NCW = RMAX / 2 + 1;  // counter words: two 16-bit counters each
   constexpr uint32_t RB = 4 * RW;  // record bytes
   extern __shared__ __align__(16) uint32_t dyn[];
-  __shared__ FinShared S;
-  uint64_t* comp = reinterpret_cast<uint64_t*>(dyn);          // M composites
-  uint32_t* cnt = dyn + 2 * M;                                // NCW words of packed counters
+  __shared__ FinShared<K> S;
+  K* comp = reinterpret_cast<K*>(dyn);                        // M composites
+  uint32_t* cnt = dyn + (sizeof(K) / 4) * M;                  // NCW words of packed counters
   uint32_t* stage = dyn;                                      // records, while delivering
   const uint32_t stage_cap = FIN_LDS_BYTES / RB;
   const KeyFmt kf = make_keyfmt(p.key_bytes);
@@ -214,7 +296,7 @@ __global__ __launch_bounds__(FWG) void k_fin_jobs(Plan p, Work w, uint8_t* rec0,
     // empty asm statement at each phase, so that the compiler recomputes the
     // per-slot conditions there instead of holding E lane masks throughout.
     uint32_t nv = m > q0 ? min(E, (m - q0 + 63) / 64) : 0u;
-    uint64_t km = kf.mlo;
+    uint64_t km = kf.mlo, kmh = kf.mhi;
     for (uint32_t v = t; v < NCW; v += FWG) cnt[v] = 0;
     for (uint32_t v = t; v < 256; v += FWG) S.h8[v] = 0;
     if (t == 0) S.nbig = 0;
@@ -230,24 +312,28 @@ __global__ __launch_bounds__(FWG) void k_fin_jobs(Plan p, Work w, uint8_t* rec0,
     }
 
     // the bits that vary over the job
-    const uint64_t ref = uniform64(rec_key<RW>(buf_load_rec<RW>(job_rsrc(((jflags & BF_TMP) ? rec1 : rec0) + jbegin * RB, RB), 0, 0), kf).lo);
-    uint64_t vo = 0;
+    const K ref = uniform_key(fkey_k<K, RW>(buf_load_rec<RW>(job_rsrc(((jflags & BF_TMP) ? rec1 : rec0) + jbegin * RB, RB), 0, 0), kf.mlo, kf.mhi));
+    K vo = zero_key<K>();
     asm volatile("" : "+v"(nv));
     km = phase_mask(kf.mlo);
+    kmh = phase_mask(kf.mhi);
 #pragma unroll
     for (uint32_t u = 0; u < E; u++)
-      if (u < nv) vo |= fkey<RW>(r[u], km) ^ ref;
+      if (u < nv) vo = vo | (fkey_k<K, RW>(r[u], km, kmh) ^ ref);
     vo = fwave_or64(vo, lane);
     if (lane == 0) S.wv[wave] = vo;
     __syncthreads();
-    uint64_t vary = 0;
+    K vary = zero_key<K>();
 #pragma unroll
-    for (int q = 0; q < FWAVES; q++) vary |= S.wv[q];
-    if (vary == 0) {
+    for (int q = 0; q < FWAVES; q++) vary = vary | S.wv[q];
+    if (is_zero(vary)) {
       // every key equal: the job is in order already
       if (jflags & BF_TMP) {
         asm volatile("" : "+v"(nv));
         km = phase_mask(kf.mlo);
+        kmh = phase_mask(kf.mhi);
+      kmh = phase_mask(kf.mhi);
+    kmh = phase_mask(kf.mhi);
 #pragma unroll
         for (uint32_t u = 0; u < E; u++)
           if (u < nv) buf_store_rec<RW>(dr, q0 * RB, u * 64 * RB, r[u]);
@@ -255,8 +341,8 @@ __global__ __launch_bounds__(FWG) void k_fin_jobs(Plan p, Work w, uint8_t* rec0,
       __syncthreads();
       continue;
     }
-    const uint32_t lo = (uint32_t)__builtin_ctzll(vary);
-    const uint32_t hi = 64u - (uint32_t)__clzll(vary);
+    const uint32_t lo = lowest_bit(vary);
+    const uint32_t hi = bit_length(vary);
     const uint32_t W = hi - lo;
     // The digit is the top D <= 12 varying bits.  A job grouped from
     // consecutive children holds only a few values of their parent's digit
@@ -268,9 +354,11 @@ __global__ __launch_bounds__(FWG) void k_fin_jobs(Plan p, Work w, uint8_t* rec0,
     if (grouped) {
       asm volatile("" : "+v"(nv));
       km = phase_mask(kf.mlo);
+      kmh = phase_mask(kf.mhi);
+    kmh = phase_mask(kf.mhi);
 #pragma unroll
       for (uint32_t u = 0; u < E; u++)
-        if (u < nv) atomicAdd(&S.h8[(uint32_t)(fkey<RW>(r[u], km) >> sh8) & 255u], 1u);
+        if (u < nv) atomicAdd(&S.h8[low32(fkey_k<K, RW>(r[u], km, kmh) >> sh8) & 255u], 1u);
       __syncthreads();
       if (wave == 0) {
         uint32_t pres = 0;
@@ -294,19 +382,19 @@ __global__ __launch_bounds__(FWG) void k_fin_jobs(Plan p, Work w, uint8_t* rec0,
     const uint32_t dsh = grouped ? sh8 - xb : hi - D;  // lowest bit of the digit's key bits
     const uint32_t rb = dsh - lo;                    // key bits below the digit
     const uint32_t ib = 32u - __clz(m - 1);          // index bits
-    if (rb + ib > 64) {  // the routing never queues such a job
+    if (rb + ib > CB) {  // the routing never queues such a job
       if (t == 0) atomicOr(&w.ctl->error, 4u);
       __syncthreads();
       continue;
     }
-    const uint64_t rmask = rb == 0 ? 0ull : ((1ull << rb) - 1);
+    const K rmask = low_mask<K>(rb);
     const uint32_t R = 1u << D;
     const uint32_t xmask = (1u << xb) - 1u;
-    auto digit_of = [&](uint64_t key) -> uint32_t {
-      if (grouped) return ((uint32_t)S.rank8[(uint32_t)(key >> sh8) & 255u] << xb) | ((uint32_t)(key >> dsh) & xmask);
-      return (uint32_t)(key >> dsh) & (R - 1);
+    auto digit_of = [&](K key) -> uint32_t {
+      if (grouped) return ((uint32_t)S.rank8[low32(key >> sh8) & 255u] << xb) | (low32(key >> dsh) & xmask);
+      return low32(key >> dsh) & (R - 1);
     };
-    auto comp_of = [&](uint64_t key, uint32_t q) -> uint64_t { return (((key >> lo) & rmask) << ib) | q; };
+    auto comp_of = [&](K key, uint32_t q) -> K { return (((key >> lo) & rmask) << ib) | q; };
     // sub-bin v occupies [end(v - 1), end(v)) once the placement is done
     auto cnt_end = [&](uint32_t v) -> uint32_t { return (cnt[v >> 1] >> (16 * (v & 1))) & 0xFFFFu; };
     auto cnt_start = [&](uint32_t v) -> uint32_t { return v ? cnt_end(v - 1) : 0u; };
@@ -315,10 +403,11 @@ __global__ __launch_bounds__(FWG) void k_fin_jobs(Plan p, Work w, uint8_t* rec0,
     // two per word: no count exceeds M < 2^16)
     asm volatile("" : "+v"(nv));
     km = phase_mask(kf.mlo);
+    kmh = phase_mask(kf.mhi);
 #pragma unroll
     for (uint32_t u = 0; u < E; u++)
       if (u < nv) {
-        const uint32_t v = digit_of(fkey<RW>(r[u], km));
+        const uint32_t v = digit_of(fkey_k<K, RW>(r[u], km, kmh));
         atomicAdd(&cnt[v >> 1], 1u << (16 * (v & 1)));
       }
     __syncthreads();
@@ -347,10 +436,11 @@ __global__ __launch_bounds__(FWG) void k_fin_jobs(Plan p, Work w, uint8_t* rec0,
     for (uint32_t q = 0; q < FWAVES; q++) bigmax = max(bigmax, S.wmax[q]);
     asm volatile("" : "+v"(nv));
     km = phase_mask(kf.mlo);
+    kmh = phase_mask(kf.mhi);
 #pragma unroll
     for (uint32_t u = 0; u < E; u++) {
       if (u < nv) {
-        const uint64_t key = fkey<RW>(r[u], km);
+        const K key = fkey_k<K, RW>(r[u], km, kmh);
         const uint32_t v = digit_of(key);
         const uint32_t sh = 16 * (v & 1);
         const uint32_t pos = (atomicAdd(&cnt[v >> 1], 1u << sh) >> sh) & 0xFFFFu;
@@ -395,24 +485,24 @@ __global__ __launch_bounds__(FWG) void k_fin_jobs(Plan p, Work w, uint8_t* rec0,
         uint32_t kind = 0;  // 0: sorted by the network, 1: split
         if (i < FIN_SPLIT_MAX) {
           // H: the key part shared by two of three samples, if any
-          const uint64_t k0 = comp[s0] >> ib, k1 = comp[(s0 + e) / 2] >> ib, k2 = comp[e - 1] >> ib;
-          const uint64_t H = (k0 == k1 || k0 == k2) ? k0 : k1;
+          const K k0 = comp[s0] >> ib, k1 = comp[(s0 + e) / 2] >> ib, k2 = comp[e - 1] >> ib;
+          const K H = (k0 == k1 || k0 == k2) ? k0 : k1;
           uint32_t nm = 0, nless = 0;
           for (uint32_t j0 = s0; j0 < e && nm <= FIN_MINORS; j0 += 64) {
             const uint32_t j = j0 + lane;
-            const uint64_t x = j < e ? comp[j] : 0ull;
+            const K x = j < e ? comp[j] : zero_key<K>();
             const bool minor = j < e && (x >> ib) != H;
             nm += (uint32_t)__popcll(__ballot(minor));
             nless += (uint32_t)__popcll(__ballot(minor && (x >> ib) < H));
           }
-          if (nm <= FIN_MINORS && pool_used + nm <= FIN_POOL_WAVE) {
-            const uint32_t at = wv * FIN_POOL_WAVE + pool_used;
+          if (nm <= FIN_MINORS && pool_used + nm <= POOL_WAVE) {
+            const uint32_t at = wv * POOL_WAVE + pool_used;
             pool_used += nm;
             {
               uint32_t put = at;
               for (uint32_t j0 = s0; j0 < e; j0 += 64) {
                 const uint32_t j = j0 + lane;
-                const uint64_t x = j < e ? comp[j] : 0ull;
+                const K x = j < e ? comp[j] : zero_key<K>();
                 const bool minor = j < e && (x >> ib) != H;
                 const uint64_t bal = __ballot(minor);
                 if (minor) S.pool[put + (uint32_t)__popcll(bal & lanemask_lt())] = x;
@@ -435,11 +525,13 @@ __global__ __launch_bounds__(FWG) void k_fin_jobs(Plan p, Work w, uint8_t* rec0,
       // (peers of a round found by ballots on the sub-bin index)
       asm volatile("" : "+v"(nv));
       km = phase_mask(kf.mlo);
+      kmh = phase_mask(kf.mhi);
+    kmh = phase_mask(kf.mhi);
 #pragma unroll
       for (uint32_t u = 0; u < E; u++) {
         uint32_t bi = FIN_SPLIT_MAX;
         if (u < nv) {
-          const uint64_t key = fkey<RW>(r[u], km);
+          const K key = fkey_k<K, RW>(r[u], km, kmh);
           const uint32_t tag = S.btag[digit_of(key)];
           if (tag && ((key >> lo) & rmask) == S.bH[tag - 1]) bi = tag - 1;
         }
@@ -470,12 +562,13 @@ __global__ __launch_bounds__(FWG) void k_fin_jobs(Plan p, Work w, uint8_t* rec0,
     // every record's slot
     asm volatile("" : "+v"(nv));
     km = phase_mask(kf.mlo);
+    kmh = phase_mask(kf.mhi);
 #pragma unroll
     for (uint32_t u = 0; u < E; u++) {
       const uint32_t q = q0 + 64 * u;
       if (u < nv) {
-        const uint64_t key = fkey<RW>(r[u], km);
-        const uint64_t x = comp_of(key, q);
+        const K key = fkey_k<K, RW>(r[u], km, kmh);
+        const K x = comp_of(key, q);
         const uint32_t v = digit_of(key);
         const uint32_t s0 = cnt_start(v), e = cnt_end(v);
         uint32_t pos;
@@ -484,7 +577,7 @@ __global__ __launch_bounds__(FWG) void k_fin_jobs(Plan p, Work w, uint8_t* rec0,
           // few words read past the sub-bin are ignored)
           uint32_t below = 0;
           for (uint32_t j = s0 & ~1u; j < e; j += 4) {
-            const uint64_t y0 = comp[j], y1 = comp[j + 1], y2 = comp[j + 2], y3 = comp[j + 3];
+            const K y0 = comp[j], y1 = comp[j + 1], y2 = comp[j + 2], y3 = comp[j + 3];
             below += (j >= s0 && y0 < x) ? 1u : 0u;
             below += (j + 1 < e && y1 < x) ? 1u : 0u;
             below += (j + 2 < e && y2 < x) ? 1u : 0u;
@@ -495,10 +588,10 @@ __global__ __launch_bounds__(FWG) void k_fin_jobs(Plan p, Work w, uint8_t* rec0,
           const uint32_t tag = S.btag[v];
           if (tag) {
             const uint32_t bi = tag - 1;
-            const uint64_t H = S.bH[bi];
+            const K H = S.bH[bi];
             const uint32_t info = S.binfo[bi];
             const uint32_t nm = info >> 16, at = info & 0xFFFFu;
-            const uint64_t xk = (key >> lo) & rmask;
+            const K xk = (key >> lo) & rmask;
             if (xk == H) {
               pos = s0 + S.bless[bi] + S.cw[wave * FIN_SPLIT_MAX + bi] + ((slot2[u / 2] >> (16 * (u & 1))) & 0xFFFFu);
             } else {
@@ -529,6 +622,8 @@ __global__ __launch_bounds__(FWG) void k_fin_jobs(Plan p, Work w, uint8_t* rec0,
       const uint32_t base = k * stage_cap;
       asm volatile("" : "+v"(nv));
       km = phase_mask(kf.mlo);
+      kmh = phase_mask(kf.mhi);
+    kmh = phase_mask(kf.mhi);
 #pragma unroll
       for (uint32_t u = 0; u < E; u++) {
         const uint32_t o = ((slot2[u / 2] >> (16 * (u & 1))) & 0xFFFFu) - base;
@@ -552,14 +647,21 @@ void launch_fin_jobs(const Plan& p, const Work& w, void* records, void* tmp, hip
   uint8_t* r0 = (uint8_t*)records;
   uint8_t* r1 = (uint8_t*)tmp;
   const uint32_t lds = FIN_LDS_BYTES;
+  const bool wide = p.key_bytes > 8;  // keys above 8 bytes need records of 12 bytes or more
   switch (p.rw) {
 #define RD_CASE(n)                                                      \
   case n:                                                               \
-    k_fin_jobs<n><<<p.grid_fin, FWG, lds, s>>>(p, w, r0, r1);           \
+    k_fin_jobs<n, false><<<p.grid_fin, FWG, lds, s>>>(p, w, r0, r1);    \
     break;
-    RD_CASE(1) RD_CASE(2) RD_CASE(3) RD_CASE(4) RD_CASE(5) RD_CASE(6) RD_CASE(7) RD_CASE(8)
-    RD_CASE(9) RD_CASE(10) RD_CASE(11) RD_CASE(12) RD_CASE(13) RD_CASE(14) RD_CASE(15) RD_CASE(16)
+#define RD_CASE_W(n)                                                    \
+  case n:                                                               \
+    if (wide) k_fin_jobs<n, true><<<p.grid_fin, FWG, lds, s>>>(p, w, r0, r1); \
+    else k_fin_jobs<n, false><<<p.grid_fin, FWG, lds, s>>>(p, w, r0, r1); \
+    break;
+    RD_CASE(1) RD_CASE(2) RD_CASE_W(3) RD_CASE_W(4) RD_CASE_W(5) RD_CASE_W(6) RD_CASE_W(7) RD_CASE_W(8)
+    RD_CASE_W(9) RD_CASE_W(10) RD_CASE_W(11) RD_CASE_W(12) RD_CASE_W(13) RD_CASE_W(14) RD_CASE_W(15) RD_CASE_W(16)
 #undef RD_CASE
+#undef RD_CASE_W
     default: break;
   }
 }

@@ -430,11 +430,12 @@ __device__ __forceinline__ uint32_t index_bits(uint64_t m) { return 64u - (uint3
 
 // Key bits a finishing job of the register kernel keeps below its digit when
 // `bit` leading bits are resolved (its keys share them): what is left after
-// the FIN_DIGIT_BITS digit.  With the index bits they must fit 64 bits.
+// the FIN_DIGIT_BITS digit.  With the index bits they must fit the
+// composite (64 bits, or 128 for keys above 8 bytes).
 __device__ __forceinline__ bool fin_fits(uint64_t m, uint32_t bit, uint32_t kbits) {
   const uint32_t rem = kbits - bit;
   const uint32_t below = rem > FIN_DIGIT_BITS ? rem - FIN_DIGIT_BITS : 0u;
-  return below + index_bits(m) <= 64;
+  return below + index_bits(m) <= fin_comp_bits(kbits);
 }
 
 // Can a bucket (or a group of consecutive children) of m records with `bit`
@@ -450,7 +451,7 @@ __device__ __forceinline__ uint64_t job_cap(const Plan& p, uint32_t bit, uint32_
   if (!p.fin_max) return p.c_fin;
   const uint32_t rem = kbits - bit;
   const uint32_t below = rem > FIN_DIGIT_BITS ? rem - FIN_DIGIT_BITS : 0u;
-  const uint32_t ibmax = 64 - below;  // at least 11
+  const uint32_t ibmax = fin_comp_bits(kbits) - below;  // at least 12
   return ibmax >= 32 ? (uint64_t)p.fin_max : min((uint64_t)p.fin_max, 1ull << ibmax);
 }
 

@@ -27,16 +27,22 @@ constexpr uint32_t NCLASS = 40;      // size classes of the queued buckets (floo
 
 // Finishing jobs held in registers (k_finish.hip): a 1024-thread workgroup
 // holds fin_records_per_thread(rw) records per thread (at most 68 words),
-// sorts composites of (key bits below an 11-bit digit, index) in LDS.
+// sorts composites of (key bits below a 12-bit digit, index) in LDS.
 constexpr uint32_t FIN_THREADS = 1024;
 constexpr uint32_t FIN_DIGIT_BITS = 12;
 __host__ __device__ constexpr uint32_t fin_records_per_thread(uint32_t rw) { return 68 / rw < 17 ? 68 / rw : 17; }
+// Keys above 8 bytes: 128-bit composites (16 bytes of LDS each), so at most
+// 8 records per thread.
+__host__ __device__ constexpr uint32_t fin_records_per_thread_wide(uint32_t rw) { return 68 / rw < 8 ? 68 / rw : 8; }
+// composite bits of a job of keys with `kbits` bits
+__host__ __device__ constexpr uint32_t fin_comp_bits(uint32_t kbits) { return kbits > 64 ? 128u : 64u; }
 constexpr uint32_t FIN_MAX_RECORDS = 17 * FIN_THREADS;
 constexpr uint32_t FIN_LDS_BYTES = 147712;  // composites of the largest job and 2^12 16-bit counters
 constexpr uint32_t FIN_LDS_BIG = 544;       // > FIN_MAX_RECORDS / 33: sub-bins above 32 records
-constexpr uint32_t FIN_STATIC_LDS = 15360;  // upper bound of the kernel's static LDS
+constexpr uint32_t FIN_STATIC_LDS = 16128;  // upper bound of the kernel's static LDS (with the dynamic part: 160 KiB)
 static_assert(FIN_LDS_BYTES >= 8 * FIN_MAX_RECORDS + 4 * ((1u << FIN_DIGIT_BITS) / 2 + 1), "LDS of a finishing job");
 static_assert(FIN_MAX_RECORDS < 65536, "16-bit counters and slots");
+static_assert(FIN_LDS_BYTES >= 16 * 8 * FIN_THREADS + 4 * ((1u << FIN_DIGIT_BITS) / 2 + 1), "LDS of a wide finishing job");
 
 // Device control block: list sizes, tickets, flags.  Cleared at the start of
 // every sort by the init kernel.

@@ -41,12 +41,13 @@ OOD_Z = 4.0  # RADULS_MLP_OOD_Z
 MODEL_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "models", "sched_mlp.rdls")
 
 # (log2 n, rec_bytes, key_bytes, distribution) of the training workloads:
-# every size class from 2^22 to 2^27 (each gives a different job structure:
+# every size class from 2^22 to 2^30 (each gives a different job structure:
 # queued buckets, one-workgroup passes, runs of small children) for each key
-# distribution, and other record shapes.  Held out: new data (other seeds)
-# of the same shapes.
+# distribution, 2^31 and 2^32 records of mixed keys, and other record
+# shapes.  Held out: new data (other seeds) of the same shapes.
 DISTS = ("uniform", "zipf", "prefix", "mix")
 TRAIN = [(lg, 16, 8, d) for lg in range(22, 31) for d in DISTS] + \
+        [(31, 16, 8, "mix"), (32, 16, 8, "mix")] + \
         [(lg, r, k, d) for lg in (23, 25, 28) for (r, k) in ((8, 8), (32, 8), (32, 16)) for d in ("uniform", "zipf", "prefix")]
 HOLDOUT = [(lg, 16, 8, d) for lg in (23, 25, 27, 29) for d in DISTS] + \
           [(24, 32, 16, "zipf"), (24, 8, 8, "mix"), (29, 32, 16, "uniform"), (29, 8, 8, "prefix")]
@@ -81,6 +82,9 @@ def collect(workloads, sample_period=3, seed=100, cap=1 << 21, per_workload=None
         if per_workload is not None:
             per_workload.append(((lg, r, k, dist), tr))
         del data, tmp
+        # give the cached blocks back: the library allocates its workspace
+        # outside torch, and the 2^32-record workloads need most of the GPU
+        torch.cuda.empty_cache()
     return np.concatenate(out) if out else np.zeros(0, dtype=ROW)
 
 
@@ -231,14 +235,46 @@ def compare(blob, configs, reps=5, seed=500):
     return out
 
 
+def regret_report(workload, blob, seed=700, period=3):
+    """Regret of the heuristic (the choices the traced sort made) and of the
+    network `blob` (evaluated on the same sampled rows) for one workload."""
+    theta, mean, scale = parse_blob(blob)
+    lg, r, k, dist = workload
+    tr = collect([workload], period, seed=seed, cap=1 << 23)
+    e = evaluate(theta, mean, scale, tr)
+    e.update({"workload": list(workload), "rows": int(len(tr))})
+    return e
+
+
+def parse_blob(blob: bytes):
+    """(theta, mean, scale) of a model blob written by raduls.model_blob."""
+    import struct
+    f, h, p_ = struct.unpack("<3I", blob[8:20])
+    a = np.frombuffer(blob[20:-4], dtype="<f4")
+    n = f * h + h + h * h + h + p_ * h + p_
+    return a[:n].copy(), a[n:n + f].copy(), a[n + f:n + 2 * f].copy()
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", required=True)
+    ap.add_argument("--regret-workload", default="",
+                    help="log2n,rec_bytes,key_bytes,dist: only report the regret of the committed network there")
     ap.add_argument("--steps", type=int, default=6000)
     ap.add_argument("--period", type=int, default=3)
     ap.add_argument("--compare-log2n", type=int, default=29)
     args = ap.parse_args(argv)
     os.makedirs(args.out, exist_ok=True)
+    if args.regret_workload:
+        lg, r, k, dist = args.regret_workload.split(",")
+        with open(MODEL_PATH, "rb") as f:
+            blob = f.read()
+        raduls.set_scheduler(raduls.SCHED_HEURISTIC)
+        rep = regret_report((int(lg), int(r), int(k), dist), blob)
+        with open(os.path.join(args.out, "regret_report.json"), "w") as f:
+            json.dump(rep, f, indent=1)
+        print(json.dumps(rep), flush=True)
+        return
     raduls.set_scheduler(raduls.SCHED_HEURISTIC)
     raduls.set_tuning(None)
     raduls.unload_model()
