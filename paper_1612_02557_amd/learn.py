@@ -9,7 +9,8 @@ bucket, and the sorter takes the cheapest feasible one:
    jobs run every feasible procedure (after one untimed warm-up run) and
    record each one's time, the others record the time of the procedure that
    ran.  Rows come from the library (64 bytes each).
-2. ``train``: masked least squares on log2(ticks) of the sampled rows, by the library's own
+2. ``train``: masked least squares on log2(ticks) of the sampled rows (at
+   most a fixed number per workload), by the library's own
    kernels (``raduls_mlp_loss_grad``, ``raduls_mlp_adam``); this module only
    batches tensors.
 3. ``regret`` on held-out sampled rows for the learned choice and for the
@@ -102,6 +103,19 @@ def dataset(tr):
     M = np.stack([(obs >> q) & 1 for q in range(P)], axis=1).astype(np.float32)
     T = np.log2(tr["ticks"].astype(np.float64) + 1.0).astype(np.float32) * M
     return X, T, M
+
+
+def balanced(parts, cap, seed=5):
+    """The sampled rows of every workload, at most `cap` of each (a random
+    subset), so that the largest sorts do not outweigh the others."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _, tr in parts:
+        s = tr[(tr["flags"] & 1) != 0]
+        if len(s) > cap:
+            s = s[np.sort(rng.choice(len(s), cap, replace=False))]
+        out.append(s)
+    return np.concatenate(out) if out else np.zeros(0, dtype=ROW)
 
 
 def init_theta(rng, bias):
@@ -263,6 +277,7 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=6000)
     ap.add_argument("--period", type=int, default=3)
     ap.add_argument("--compare-log2n", type=int, default=29)
+    ap.add_argument("--per-workload", type=int, default=100_000, help="sampled training rows kept per workload")
     args = ap.parse_args(argv)
     os.makedirs(args.out, exist_ok=True)
     if args.regret_workload:
@@ -279,10 +294,11 @@ def main(argv=None):
     raduls.set_tuning(None)
     raduls.unload_model()
     t0 = time.time()
-    tr = collect(TRAIN, args.period, seed=100)
+    tr_parts = []
+    tr = collect(TRAIN, args.period, seed=100, per_workload=tr_parts)
     ho_parts = []
     ho = collect(HOLDOUT, args.period, seed=300, per_workload=ho_parts)
-    X, T, M = dataset(tr)
+    X, T, M = dataset(balanced(tr_parts, args.per_workload))
     log(f"{len(tr)} training rows, {len(ho)} held-out rows; training")
     theta, mean, scale, hist = train(X, T, M, steps=args.steps)
     blob = raduls.model_blob(theta, mean, scale)
@@ -306,7 +322,7 @@ def main(argv=None):
     lg = args.compare_log2n
     cmp_ = compare(blob, [(lg, 16, 8, d) for d in ("uniform", "zipf", "prefix", "mix")] +
                    [(lg - 1, 32, 16, "zipf"), (lg, 8, 8, "mix")])
-    report = {"train_rows": int(len(tr)), "holdout_rows": int(len(ho)), "loss_history": hist,
+    report = {"train_rows": int(len(tr)), "fit_rows": int(len(X)), "holdout_rows": int(len(ho)), "loss_history": hist,
               "train_eval": ev_train, "holdout_eval": ev_hold, "holdout_per_workload": per, "end_to_end": cmp_,
               "train_workloads": [list(w) for w in TRAIN], "holdout_workloads": [list(w) for w in HOLDOUT],
               "seconds": time.time() - t0}
