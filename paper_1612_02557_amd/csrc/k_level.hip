@@ -753,7 +753,12 @@ __global__ __launch_bounds__(WG) void k_scatter(Plan p, Work w, uint32_t level, 
   constexpr uint32_t RMAX = 1u << DB;
   constexpr uint32_t IPT_MAX = RW >= 2 ? 64 / RW : 32;  // at most 64 words of records per thread
   extern __shared__ __align__(16) uint32_t stage[];
-  __shared__ uint32_t wcnt[NWAVES * RMAX];
+  // per-wave digit counters; with digits of at most 8 bits two sets, used by
+  // alternate tiles, so a tile's set is cleared during the next tile and no
+  // barrier closes the write-out
+  constexpr bool DBUF = DB <= 8;
+  constexpr uint32_t WCN = NWAVES * RMAX;
+  __shared__ uint32_t wcnt[(DBUF ? 2 : 1) * WCN];
   __shared__ uint32_t toff[RMAX + 1];
   __shared__ uint64_t gbase[RMAX];
   __shared__ uint32_t sscan[NWAVES + 1];
@@ -802,9 +807,10 @@ __global__ __launch_bounds__(WG) void k_scatter(Plan p, Work w, uint32_t level, 
     for (uint32_t j = 0; j < IPT_MAX; j++)
       if (j < IPT) rec[j] = buf_load_rec<RW>(sr, voff, j * 64 * RB);
   };
-  for (uint32_t i = threadIdx.x; i < NWAVES * RMAX; i += WG) wcnt[i] = 0;
+  for (uint32_t i = threadIdx.x; i < (DBUF ? 2 : 1) * WCN; i += WG) wcnt[i] = 0;
   if (threadIdx.x == 0) claim();
   __syncthreads();
+  uint32_t par = 0;  // counter set of the current tile
   uint64_t ticket = uniform64(sticket);
   uint32_t b = uniform32(sb);
   load_tile(ticket, b);
@@ -835,6 +841,7 @@ __global__ __launch_bounds__(WG) void k_scatter(Plan p, Work w, uint32_t level, 
 
     // one register of rank state per record (the digit is recomputed from
     // the record where it is needed): more waves fit the register file
+    uint32_t* const wc = wcnt + par * WCN;
     uint32_t rk[IPT_MAX];
     uint64_t wbase = r0 + (uint64_t)wave * per_wave;
 #pragma unroll
@@ -843,7 +850,7 @@ __global__ __launch_bounds__(WG) void k_scatter(Plan p, Work w, uint32_t level, 
         uint64_t i = wbase + (uint64_t)j * 64 + lane;
         bool valid = i < bend;
         uint32_t v = valid ? key_digit(rec_key<RW>(rec[j], kf), shift, mask, kf) : 0u;
-        rk[j] = rank_issue32(&wcnt[wave * RMAX], v, d, valid);
+        rk[j] = rank_issue32(&wc[wave * RMAX], v, d, valid);
       }
     }
 #pragma unroll
@@ -852,14 +859,36 @@ __global__ __launch_bounds__(WG) void k_scatter(Plan p, Work w, uint32_t level, 
     __syncthreads();
     // the tile's digit counts: per-wave bases, and the tile's own digit
     // starts (an exclusive scan) for staging
-    for (uint32_t v = threadIdx.x; v < R; v += WG) {
-      uint32_t s = 0;
+    if constexpr (DBUF) {
+      // the other set (the previous tile's) is free: clear it for the next tile
+      for (uint32_t i = threadIdx.x; i < WCN; i += WG) wcnt[(par ^ 1u) * WCN + i] = 0;
+      // thread v takes digit v (R <= 256 = WG): bases over the waves, then
+      // the tile's exclusive scan over the digits
+      const uint32_t v = threadIdx.x;
+      uint32_t tot = 0;
+      if (v < R) {
 #pragma unroll
-      for (int q = 0; q < NWAVES; q++) { uint32_t c = wcnt[q * RMAX + v]; wcnt[q * RMAX + v] = s; s += c; }
-      toff[v] = s;
+        for (int q = 0; q < NWAVES; q++) { const uint32_t c = wc[q * RMAX + v]; wc[q * RMAX + v] = tot; tot += c; }
+      }
+      uint32_t wt;
+      const uint32_t ex = wave_excl_scan(tot, &wt);
+      if (lane == 0) sscan[wave] = wt;
+      __syncthreads();
+      uint32_t base = 0;
+#pragma unroll
+      for (uint32_t q = 0; q < NWAVES; q++) base += q < wave ? sscan[q] : 0u;
+      if (v < R) toff[v] = base + ex;
+      __syncthreads();
+    } else {
+      for (uint32_t v = threadIdx.x; v < R; v += WG) {
+        uint32_t s = 0;
+#pragma unroll
+        for (int q = 0; q < NWAVES; q++) { uint32_t c = wc[q * RMAX + v]; wc[q * RMAX + v] = s; s += c; }
+        toff[v] = s;
+      }
+      __syncthreads();
+      block_excl_scan_lds(toff, R, sscan);
     }
-    __syncthreads();
-    block_excl_scan_lds(toff, R, sscan);
     // stage the records in LDS ordered by digit
 #pragma unroll
     for (uint32_t j = 0; j < IPT_MAX; j++) {
@@ -867,7 +896,7 @@ __global__ __launch_bounds__(WG) void k_scatter(Plan p, Work w, uint32_t level, 
         uint64_t i = wbase + (uint64_t)j * 64 + lane;
         if (i < bend) {
           const uint32_t v = key_digit(rec_key<RW>(rec[j], kf), shift, mask, kf);
-          uint32_t pos = toff[v] + wcnt[wave * RMAX + v] + rk[j];
+          uint32_t pos = toff[v] + wc[wave * RMAX + v] + rk[j];
           lds_put<RW>(stage, pos, rec[j]);
         }
       }
@@ -890,8 +919,14 @@ __global__ __launch_bounds__(WG) void k_scatter(Plan p, Work w, uint32_t level, 
       uint32_t v = key_digit(rec_key<RW>(r, kf), shift, mask, kf);
       store_rec<RW>(dst, gbase[v] + q, r, nt);
     }
-    for (uint32_t i = threadIdx.x; i < NWAVES * RMAX; i += WG) wcnt[i] = 0;
-    __syncthreads();
+    if constexpr (DBUF) {
+      // the next tile's first barrier comes after every thread's write-out
+      // here, before its staging reuses the stage
+      par ^= 1u;
+    } else {
+      for (uint32_t i = threadIdx.x; i < WCN; i += WG) wcnt[i] = 0;
+      __syncthreads();
+    }
   }
 }
 
