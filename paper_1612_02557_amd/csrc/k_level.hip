@@ -747,11 +747,15 @@ __global__ __launch_bounds__(WG) void k_tile_scan(Plan p, Work w, uint32_t level
 // The tile stages its records in LDS ordered by digit and writes each
 // digit's run contiguously at the offset the tile-offset scan computed for
 // it, so no tile waits for another.
-template <int RW, int DB>
+// SMALL: tiles of at most 32 words of records per thread (half the
+// registers and staging), so that more workgroups share a CU.
+template <int RW, int DB, bool SMALL>
 __global__ __launch_bounds__(WG) void k_scatter(Plan p, Work w, uint32_t level, const uint8_t* rec0,
                                                 uint8_t* rec0w, const uint8_t* rec1, uint8_t* rec1w) {
   constexpr uint32_t RMAX = 1u << DB;
-  constexpr uint32_t IPT_MAX = RW >= 2 ? 64 / RW : 32;  // at most 64 words of records per thread
+  // at most 64 (SMALL: 32) words of records per thread, and 32 records (the
+  // plan's tiles never hold more per thread)
+  constexpr uint32_t IPT_MAX = RW >= 2 ? (SMALL ? 32 : 64) / RW : 32;
   extern __shared__ __align__(16) uint32_t stage[];
   // per-wave digit counters; with digits of at most 8 bits two sets, used by
   // alternate tiles, so a tile's set is cleared during the next tile and no
@@ -1085,10 +1089,17 @@ void launch_level_scatter(const Plan& p, const Work& w, uint32_t level, void* re
   uint8_t* w0 = (uint8_t*)records;
   uint8_t* w1 = (uint8_t*)tmp;
   size_t stage = (size_t)p.tile * p.rec_bytes;
+  // tiles of at most 32 words per thread take the variant with half the
+  // registers; its workgroups are more per CU
+  const bool small = (uint64_t)p.tile * p.rw <= 32ull * WG;
+  const uint32_t grid = small ? 2 * p.grid_scatter : p.grid_scatter;
   switch (p.rw * 2 + (p.d_big > 8 ? 1 : 0)) {
 #define RD_CASE(n)                                                                                              \
-  case 2 * n: k_scatter<n, 8><<<p.grid_scatter, WG, stage, s>>>(p, w, level, r0, w0, r1, w1); break;          \
-  case 2 * n + 1: k_scatter<n, 11><<<p.grid_scatter, WG, stage, s>>>(p, w, level, r0, w0, r1, w1); break;
+  case 2 * n:                                                                                                   \
+    if (small) k_scatter<n, 8, true><<<grid, WG, stage, s>>>(p, w, level, r0, w0, r1, w1);                     \
+    else k_scatter<n, 8, false><<<grid, WG, stage, s>>>(p, w, level, r0, w0, r1, w1);                          \
+    break;                                                                                                      \
+  case 2 * n + 1: k_scatter<n, 11, false><<<grid, WG, stage, s>>>(p, w, level, r0, w0, r1, w1); break;
     RD_CASE(1) RD_CASE(2) RD_CASE(3) RD_CASE(4) RD_CASE(5) RD_CASE(6) RD_CASE(7) RD_CASE(8)
     RD_CASE(9) RD_CASE(10) RD_CASE(11) RD_CASE(12) RD_CASE(13) RD_CASE(14) RD_CASE(15) RD_CASE(16)
 #undef RD_CASE
