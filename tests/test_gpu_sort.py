@@ -213,3 +213,41 @@ def test_register_finish_duplicates(R, case, rng):
         keys[u < 0.4] = np.uint64(3)
         keys[u > 0.6] = np.uint64(3) + np.uint64(1 << 20)
     check(R, _dup_records(keys), 8, f"register finish {case} n={len(keys)}")
+
+
+def _dup_records16(hi, lo, r=32):
+    n = len(hi)
+    rec = np.zeros((n, r), dtype=np.uint8)
+    rec[:, 0:8] = np.asarray(lo, dtype="<u8").view(np.uint8).reshape(n, 8)
+    rec[:, 8:16] = np.asarray(hi, dtype="<u8").view(np.uint8).reshape(n, 8)
+    rec[:, 16:24] = np.arange(n, dtype="<u8").view(np.uint8).reshape(n, 8)
+    return rec
+
+
+@pytest.mark.parametrize("case", ["kmer_like", "heavy_key", "low_word_only", "high_word_only", "straddle"])
+def test_register_finish_wide_keys(R, case, rng):
+    """Jobs of 16-byte keys finished with 128-bit composites: runs of equal
+    keys, keys that differ only in the low or only in the high word, and
+    varying bits on both sides of the word boundary, against the oracle."""
+    n = 300_000
+    if case == "kmer_like":       # few distinct random keys, many copies of each
+        pool_hi = rng.integers(0, 1 << 64, 3000, dtype=np.uint64)
+        pool_lo = rng.integers(0, 1 << 64, 3000, dtype=np.uint64)
+        j = rng.integers(0, 3000, n)
+        hi, lo = pool_hi[j], pool_lo[j]
+    elif case == "heavy_key":
+        hi = rng.integers(0, 1 << 64, n, dtype=np.uint64)
+        lo = rng.integers(0, 1 << 64, n, dtype=np.uint64)
+        heavy = rng.random(n) < 0.6
+        hi[heavy], lo[heavy] = np.uint64(0x0123456789ABCDEF), np.uint64(0xFEDCBA9876543210)
+    elif case == "low_word_only":
+        hi = np.full(n, 0xABCDEF0123456789, dtype=np.uint64)
+        lo = rng.integers(0, 1 << 64, n, dtype=np.uint64)
+    elif case == "high_word_only":
+        hi = rng.integers(0, 1 << 64, n, dtype=np.uint64)
+        lo = np.full(n, 77, dtype=np.uint64)
+    else:                         # 20 varying bits around bit 64
+        v = rng.integers(0, 1 << 20, n, dtype=np.uint64)
+        hi = np.uint64(0x5555000000000000) | (v >> np.uint64(10))
+        lo = np.uint64(0x00000000000000FF) | ((v & np.uint64(1023)) << np.uint64(54))
+    check(R, _dup_records16(hi, lo), 16, f"register finish wide {case} n={n}")
