@@ -120,6 +120,25 @@ typedef struct raduls_stats {
 int raduls_sort(void* records, void* tmp, uint64_t n, uint32_t rec_bytes, uint32_t key_bytes,
                 void* stream);
 
+/* Sort n records in `records` (device, 16-byte aligned) by key, ascending,
+ * with no caller buffer besides the records: the in-place MSD variant the
+ * paper sets its method against (Sec. 2, in-place radix sorting with a
+ * speculative permutation and a repair step).  Each level partitions every
+ * bucket within its own records, moving whole blocks of records of one
+ * digit (at most 512 bytes each); buckets then finish in registers in
+ * place.  NOT stable: records with equal keys end in an unspecified order
+ * (the result's keys are those of raduls_sort, its records a permutation of
+ * the input).  The library's own workspace
+ * (raduls_inplace_workspace_bytes) replaces the n*rec_bytes of `tmp`.
+ * n <= 1 returns RADULS_OK at once.  Same argument checks and error codes as
+ * raduls_sort; device-side failures (a bounded wait that gave up, a
+ * capacity or cursor check) are reported by raduls_sync_check. */
+int raduls_sort_inplace(void* records, uint64_t n, uint32_t rec_bytes, uint32_t key_bytes, void* stream);
+
+/* Bytes of library workspace a raduls_sort_inplace of n records uses
+ * (0 for an unsupported shape). */
+size_t raduls_inplace_workspace_bytes(uint64_t n, uint32_t rec_bytes, uint32_t key_bytes);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * sort as raduls_sort, with the same arguments, results and argument

@@ -13,7 +13,7 @@ BUILD = os.path.join(HERE, "_build")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("RADULS_ARCH", "gfx950")
-SOURCES = ["k_level.hip", "k_small.hip", "k_finish.hip", "k_count.hip", "k_search.hip", "k_mlp.hip", "api.cpp"]
+SOURCES = ["k_level.hip", "k_small.hip", "k_finish.hip", "k_count.hip", "k_search.hip", "k_inplace.hip", "k_mlp.hip", "api.cpp"]
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     # keep the compiler from forming packed fp32 instructions

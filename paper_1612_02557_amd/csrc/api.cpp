@@ -68,6 +68,9 @@ struct DeviceState {
   int cu_count = 256;
   uint8_t* runs_ws = nullptr;     // run counting: control block + look-back words
   size_t runs_bytes = 0;
+  uint8_t* ip_base = nullptr;     // in-place levels: stripes, side buffer, child ranges, bits
+  size_t ip_bytes = 0;
+  rd::IpWork ipw{};
 };
 
 std::map<int, DeviceState> g_dev;
@@ -624,6 +627,144 @@ int enqueue_runs(const void* sorted, uint64_t n, uint32_t r, uint32_t k, void* u
   return mark_done(s, st);
 }
 
+// ---- in-place sorting --------------------------------------------------------
+
+// Blocks per stripe of the in-place levels; tests may lower it (through the
+// environment, read per call) so that small inputs take the multi-stripe path.
+uint32_t ip_slb() {
+  uint32_t v = rd::IP_SLB;
+  if (const char* e = getenv("RADULS_TEST_IP_SLB")) {
+    const unsigned long x = strtoul(e, nullptr, 10);
+    if (x >= 1 && x <= rd::IP_SLB) v = (uint32_t)x;
+  }
+  return v;
+}
+
+struct IpLayout {
+  size_t ctl, large, stripe_first, medium, nbfull, lcnt, side, prot, W, rbase, rlim, rf, re, rF, rL, rinit,
+      chunk_start, done, mscratch, total;
+  uint64_t cap_large, cap_stripes, cap_ranges, done_words;
+};
+
+// A large bucket holds more than SL = slb * B records, so there are at most
+// n / SL of them, and their stripes (ceil(count / SL) each) number at most
+// 2 n / SL + 2.
+IpLayout ip_layout_of(uint64_t n, uint32_t rw, uint64_t cap_big, uint32_t grid_medium, uint32_t slb) {
+  IpLayout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
+  const uint64_t B = rd::ip_block_records(rw);
+  const uint64_t SL = (uint64_t)slb * B;
+  L.cap_large = n / SL + 1;
+  L.cap_stripes = 2 * (n / SL) + 2;
+  L.cap_ranges = L.cap_large * rd::IP_R;
+  L.done_words = (n / B + 2) / 32 + 2;
+  L.ctl = take(sizeof(rd::IpCtl));
+  L.large = take(L.cap_large * 4);
+  L.stripe_first = take((L.cap_large + 1) * 4);
+  L.medium = take(cap_big * 4);
+  L.nbfull = take(L.cap_stripes * 4);
+  L.lcnt = take(L.cap_stripes * rd::IP_R * 2);
+  L.side = take(L.cap_stripes * rd::IP_R * rd::IP_BLOCK_BYTES);
+  L.prot = take(L.cap_ranges * rd::IP_BLOCK_BYTES);
+  L.W = take(L.cap_ranges * 8);
+  L.rbase = take(L.cap_ranges * 8);
+  L.rlim = take(L.cap_ranges * 8);
+  L.rf = take(L.cap_ranges * 4);
+  L.re = take(L.cap_ranges * 4);
+  L.rF = take(L.cap_ranges * 4);
+  L.rL = take(L.cap_ranges * 4);
+  L.rinit = take(L.cap_ranges * 4);
+  L.chunk_start = take((L.cap_ranges + 1) * 4);
+  L.done = take(L.done_words * 4 + 8);
+  L.mscratch = take((size_t)grid_medium * rd::IP_R * rd::IP_BLOCK_BYTES);
+  L.total = o;
+  return L;
+}
+
+int ensure_ip_workspace(DeviceState& s, const Plan& p) {
+  const uint32_t slb = ip_slb();
+  const uint32_t gm = (uint32_t)s.cu_count;
+  const IpLayout L = ip_layout_of(p.n, p.rw, p.cap_big, gm, slb);
+  if (L.total > s.ip_bytes) {
+    if (s.ip_base) {
+      HIPCHK(hipDeviceSynchronize());
+      hipFree(s.ip_base);
+      s.ip_base = nullptr;
+      s.ip_bytes = 0;
+    }
+    const size_t want = L.total + L.total / 8;
+    if (hipMalloc(&s.ip_base, want) != hipSuccess) {
+      (void)hipGetLastError();
+      s.ip_base = nullptr;
+      return fail(RADULS_ENOMEM, "in-place workspace allocation failed");
+    }
+    s.ip_bytes = want;
+  }
+  uint8_t* b = s.ip_base;
+  rd::IpWork& w = s.ipw;
+  w.ctl = (rd::IpCtl*)(b + L.ctl);
+  w.large = (uint32_t*)(b + L.large);
+  w.stripe_first = (uint32_t*)(b + L.stripe_first);
+  w.medium = (uint32_t*)(b + L.medium);
+  w.nbfull = (uint32_t*)(b + L.nbfull);
+  w.lcnt = (uint16_t*)(b + L.lcnt);
+  w.side = b + L.side;
+  w.prot = b + L.prot;
+  w.W = (uint64_t*)(b + L.W);
+  w.rbase = (uint64_t*)(b + L.rbase);
+  w.rlim = (uint64_t*)(b + L.rlim);
+  w.rf = (uint32_t*)(b + L.rf);
+  w.re = (uint32_t*)(b + L.re);
+  w.rF = (uint32_t*)(b + L.rF);
+  w.rL = (uint32_t*)(b + L.rL);
+  w.rinit = (uint32_t*)(b + L.rinit);
+  w.chunk_start = (uint32_t*)(b + L.chunk_start);
+  w.done = (uint32_t*)(b + L.done);
+  w.mscratch = b + L.mscratch;
+  w.cap_large = L.cap_large;
+  w.cap_stripes = L.cap_stripes;
+  w.cap_ranges = L.cap_ranges;
+  w.done_words = L.done_words;
+  w.grid_medium = gm;
+  w.slb = slb;
+  return RADULS_OK;
+}
+
+// Plan of an in-place sort: 8-bit digits, every bucket that is not a
+// finishing job takes another level (k levels resolve every key bit, so no
+// bucket is left for the single-workgroup queue), and none of the
+// out-of-place stages' tile arrays, queues or stacks.
+int make_inplace_plan(uint64_t n, uint32_t r, uint32_t k, int cus, Plan& p) {
+  raduls_tuning t = default_tuning(r, k, n);
+  t.big_digit_bits = 8;
+  t.reg_finish = 1;
+  t.big_rule = 1;
+  p = make_plan(n, r, k, t, cus, 0, true);
+  if (!p.fin_max) return fail(RADULS_EUNSUPPORTED, "in-place sorting needs the register finishing kernel");
+  p.inplace = 1;
+  p.lmax = std::min<uint32_t>(k + 1, rd::LMAX);
+  p.cap_small = 1;
+  p.cap_copy = 1;
+  p.max_tiles = 1;
+  p.stack_cap = 1;
+  return RADULS_OK;
+}
+
+void enqueue_inplace(DeviceState& s, const Plan& p, void* records, hipStream_t st) {
+  const Work& w = s.work;
+  const rd::IpWork& iw = s.ipw;
+  rd::launch_init(w, st);
+  rd::launch_zero(iw.ctl, sizeof(rd::IpCtl), st);
+  rd::launch_seed_single(p, w, st);
+  for (uint32_t l = 0; l < p.lmax; l++) {
+    rd::launch_level_prep(p, w, l, st);
+    rd::launch_ip_level(p, w, iw, l, records, s.cu_count, st);
+  }
+  rd::launch_small(p, w, records, records, st);
+  rd::launch_fin_jobs(p, w, records, records, st);
+}
+
 }  // namespace
 
 extern "C" {
@@ -664,6 +805,52 @@ int raduls_sort(void* records, void* tmp, uint64_t n, uint32_t rec_bytes, uint32
   g_stats.last_records = n;
   g_stats.last_levels = p.lmax;
   return mark_done(s, st);
+}
+
+int raduls_sort_inplace(void* records, uint64_t n, uint32_t rec_bytes, uint32_t key_bytes, void* stream) {
+  int rc = check_shape(rec_bytes, key_bytes);
+  if (rc) return rc;
+  if (n <= 1) return RADULS_OK;
+  if (!records) return fail(RADULS_EINVAL, "null records");
+  if (n >= (1ull << 40)) return fail(RADULS_EUNSUPPORTED, "n must be below 2^40");
+  if ((uintptr_t)records & 15) return fail(RADULS_EINVAL, "records must be 16-byte aligned");
+  std::lock_guard<std::mutex> lock(g_mu);
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  DeviceState& s = state_for(dev);
+  hipStream_t st = (hipStream_t)stream;
+  Plan p;
+  rc = make_inplace_plan(n, rec_bytes, key_bytes, s.cu_count, p);
+  if (rc) return rc;
+  Layout L;
+  rc = order_after_previous(s, st);
+  if (rc) return rc;
+  rc = prepare(s, p, L, st);
+  if (rc) return rc;
+  rc = ensure_ip_workspace(s, p);
+  if (rc) return rc;
+  if (g_timing) {
+    if (!s.t0) { HIPCHK(hipEventCreate(&s.t0)); HIPCHK(hipEventCreate(&s.t1)); }
+    HIPCHK(hipEventRecord(s.t0, st));
+  }
+  s.ph_id.clear();
+  s.ph_valid = false;
+  enqueue_inplace(s, p, records, st);
+  s.last_plan = p;
+  HIPCHK(hipGetLastError());
+  if (g_timing) { HIPCHK(hipEventRecord(s.t1, st)); s.timed = true; }
+  s.epochs_used += rd::LMAX + 1;
+  g_stats.last_records = n;
+  g_stats.last_levels = p.lmax;
+  return mark_done(s, st);
+}
+
+size_t raduls_inplace_workspace_bytes(uint64_t n, uint32_t rec_bytes, uint32_t key_bytes) {
+  if (check_shape(rec_bytes, key_bytes)) return 0;
+  Plan p;
+  if (make_inplace_plan(std::max<uint64_t>(n, 2), rec_bytes, key_bytes, 256, p)) return 0;
+  const Layout L = layout_of(p);
+  return L.total + L.status_total + ip_layout_of(p.n, p.rw, p.cap_big, 256, rd::IP_SLB).total;
 }
 
 int raduls_sort_noalloc(void* records, void* tmp, uint64_t n, uint32_t rec_bytes, uint32_t key_bytes, void* stream) {
@@ -954,6 +1141,17 @@ int raduls_sync_check(void* stream) {
       if (rc == RADULS_OK) rc = fail(RADULS_EDEVICE, "run counting: look-back wait limit reached");
     }
   }
+  if (it != g_dev.end() && it->second.ip_base) {
+    rd::IpCtl c;
+    HIPCHK(hipMemcpy(&c, it->second.ipw.ctl, sizeof(c), hipMemcpyDeviceToHost));
+    if (c.error) {
+      const uint32_t zero = 0;
+      HIPCHK(hipMemcpy(&it->second.ipw.ctl->error, &zero, 4, hipMemcpyHostToDevice));
+      if (rc == RADULS_OK)
+        rc = fail(RADULS_EDEVICE, (c.error & 2u) ? "in-place level: wait limit reached"
+                                                  : "in-place level: capacity or cursor check failed");
+    }
+  }
   if (dev >= 0 && dev < NOALLOC_MAX_DEVICES && g_noalloc[dev].ctl) {
     int rc2 = check_ctl(g_noalloc[dev].ctl);
     if (rc == RADULS_OK) rc = rc2;
@@ -1171,6 +1369,7 @@ void raduls_release(void) {
     if (s.base) hipFree(s.base);
     if (s.status_base) hipFree(s.status_base);
     if (s.runs_ws) hipFree(s.runs_ws);
+    if (s.ip_base) hipFree(s.ip_base);
     if (s.model) hipFree(s.model);
     if (s.last_done) hipEventDestroy(s.last_done);
     if (s.t0) hipEventDestroy(s.t0);

@@ -562,7 +562,7 @@ __global__ __launch_bounds__(WG) void k_scan(Plan p, Work w, uint32_t level) {
         ch.count = m;
         ch.parent = B.count;
         ch.bit = m == gfc[t] ? B.bit + d : B.bit;
-        ch.flags = ((B.flags & BF_TMP) ^ BF_TMP) | (m == gfc[t] ? 0u : BF_GROUP);
+        ch.flags = (p.inplace ? 0u : ((B.flags & BF_TMP) ^ BF_TMP)) | (m == gfc[t] ? 0u : BF_GROUP);
         direct = job_ok(p, m, ch.bit, kf.kbits);
         if (!direct) route_bucket(p, w, level + 1, ch, kf.kbits);
       }
@@ -590,7 +590,7 @@ __global__ __launch_bounds__(WG) void k_scan(Plan p, Work w, uint32_t level) {
         ch.count = c;
         ch.parent = B.count;
         ch.bit = B.bit + d;
-        ch.flags = (B.flags & BF_TMP) ^ BF_TMP;
+        ch.flags = p.inplace ? 0u : ((B.flags & BF_TMP) ^ BF_TMP);
         route_bucket(p, w, level + 1, ch, kf.kbits);
       }
       run += c;

@@ -110,7 +110,7 @@ struct Plan {
   uint32_t spin_limit;     // polls a look-back wait makes before it gives up
   uint32_t fin_max;        // largest job finished in registers (0: jobs go to the LDS path)
   uint32_t grid_fin;       // workgroups of the register-finishing kernel
-  uint32_t pad0;
+  uint32_t inplace;        // 1: levels partition in place (no tmp; children stay in the records)
   uint64_t trace_cap;
 };
 
@@ -137,6 +137,57 @@ struct Work {
   uint64_t* trace_count;
   uint64_t* counts_out;       // partition: histogram for the caller, or null
   uint32_t* epoch_counter;    // look-back epochs handed out so far
+};
+
+// ---- in-place levels (k_inplace.hip) ---------------------------------------
+// A level partitions each of its buckets within its own records.  Records
+// are moved in blocks of ip_block_records(rw) records (at most 512 bytes):
+// each stripe of a bucket is first rewritten as whole blocks of one digit
+// each, which then move to their children's ranges; the few records that
+// do not fill a block (at most a block per digit and stripe) wait in a side
+// buffer and fill the children's edges at the end.
+constexpr uint32_t IP_WG = 1024;          // threads of the in-place workgroups
+constexpr uint32_t IP_R = 256;            // digits of a level (8 bits)
+constexpr uint32_t IP_BLOCK_BYTES = 512;  // bytes of a block, at most
+constexpr uint32_t IP_SLB = 32768;        // blocks per stripe; a bucket of at most one stripe is one workgroup's
+constexpr uint32_t IP_MAX_STRIPES = 8192; // stripes of one bucket, at most
+constexpr uint32_t IP_CHUNK = 16;         // block reads per claim of the permutation
+constexpr uint32_t IP_BIAS = 1u << 30;    // added to the read cursor so that extra decrements never borrow
+__host__ __device__ constexpr uint32_t ip_block_records(uint32_t rw) { return IP_BLOCK_BYTES / (4 * rw); }
+
+struct IpCtl {
+  uint32_t nlarge;         // buckets of the level split into stripes
+  uint32_t nmedium;        // buckets of the level partitioned by one workgroup
+  uint32_t nstripes;       // stripes of the large buckets
+  uint32_t nranges;        // child ranges of the large buckets (256 each)
+  uint32_t stripe_ticket, medium_ticket, chunk_ticket;
+  uint32_t nchunks, stride;
+  uint32_t error;          // bit 0: capacity, bit 1: wait limit, bit 2: cursor out of its range
+};
+
+struct IpWork {
+  IpCtl* ctl;
+  uint32_t* large;         // cap_large: list entry of each large bucket
+  uint32_t* stripe_first;  // cap_large + 1: first stripe of each large bucket
+  uint32_t* medium;        // cap_big: list entry of each medium bucket
+  uint32_t* nbfull;        // cap_stripes: blocks written by each stripe
+  uint16_t* lcnt;          // cap_stripes x IP_R: records left over per stripe and digit
+  uint8_t* side;           // cap_stripes x IP_R x IP_BLOCK_BYTES: those records
+  uint8_t* prot;           // cap_ranges x IP_BLOCK_BYTES: records of a child's last block past the child's end
+  uint64_t* W;             // cap_ranges: write cursor << 32 | (read cursor + IP_BIAS), in block slots
+  uint64_t* rbase;         // cap_ranges: first record of each child, relative to its bucket
+  uint64_t* rlim;          // cap_ranges: end of each child, relative to its bucket
+  uint32_t* rf;            // cap_ranges: first block slot starting inside the child
+  uint32_t* re;            // cap_ranges: end of the child's slots
+  uint32_t* rF;            // cap_ranges: blocks of the child's digit
+  uint32_t* rL;            // cap_ranges: records of the child left over in the stripes
+  uint32_t* rinit;         // cap_ranges: read cursor before the permutation
+  uint32_t* chunk_start;   // cap_ranges + 1: permutation chunks of each range (prefix)
+  uint32_t* done;          // done_words: one bit per block of the records, set once its reader has it
+  uint8_t* mscratch;       // grid_medium x IP_R x IP_BLOCK_BYTES: protruding records of the medium kernel
+  uint64_t cap_large, cap_stripes, cap_ranges, done_words;
+  uint32_t grid_medium;
+  uint32_t slb;            // blocks per stripe (IP_SLB; smaller only in tests)
 };
 
 }  // namespace rd

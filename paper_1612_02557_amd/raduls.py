@@ -96,6 +96,8 @@ _SIGS = {
     "raduls_phase_times": (_i32, [ctypes.POINTER(ctypes.c_double), _u32]),
     "raduls_last_work": (_i32, [ctypes.POINTER(_u64), _u32]),
     "raduls_workspace_bytes": (ctypes.c_size_t, [_u64, _u32, _u32]),
+    "raduls_sort_inplace": (_i32, [_vp, _u64, _u32, _u32, _vp]),
+    "raduls_inplace_workspace_bytes": (ctypes.c_size_t, [_u64, _u32, _u32]),
     "raduls_status_string": (ctypes.c_char_p, [_i32]),
     "raduls_last_error_message": (ctypes.c_char_p, []),
     "raduls_release": (None, []),
@@ -188,6 +190,27 @@ def sort(records, key_bytes: int, tmp=None, stream=None, check: bool = False):
     if check:
         sync_check(stream)
     return records
+
+
+def sort_inplace(records, key_bytes: int, stream=None, check: bool = False):
+    """Sort ``records`` by key within their own memory (``raduls_sort_inplace``):
+    no ``tmp``; NOT stable -- records with equal keys end in an unspecified
+    order.  ``check`` as for ``sort``."""
+    records = _records(records)
+    n, r = records.shape
+    _check(lib().raduls_sort_inplace(records.data_ptr(), n, r, key_bytes, _stream(stream)))
+    if check:
+        sync_check(stream)
+    return records
+
+
+def sort_inplace_ptr(records_ptr: int, n: int, rec_bytes: int, key_bytes: int, stream: int) -> int:
+    """Raw call returning the status code (for argument-error tests)."""
+    return lib().raduls_sort_inplace(records_ptr, n, rec_bytes, key_bytes, stream)
+
+
+def inplace_workspace_bytes(n: int, rec_bytes: int, key_bytes: int) -> int:
+    return int(lib().raduls_inplace_workspace_bytes(n, rec_bytes, key_bytes))
 
 
 NOALLOC_SCRATCH_BYTES = 64 << 20

@@ -101,3 +101,41 @@ def exact_index_check(out_dev, inp_dev, rec_bytes: int = 16, key_bytes: int = 8,
         prev = [c[-1:].clone() for c in cols]
         del cols, ok
     return None
+
+
+def unstable_index_check(out_dev, inp_dev, key_bytes: int = 8, chunk: int = 1 << 27):
+    """Exactness test of a device sort that need not be stable, on the device.
+
+    Records whose key is 8 or 16 bytes followed by the input index (8 bytes):
+    the output is a correct unstable sort of the input iff every output record
+    equals the input record its payload names, every input index occurs
+    (then the output is a permutation of the input), and the keys never
+    decrease along the output.  Returns None (exact) or a message."""
+    import torch
+    n = out_dev.shape[0]
+    if n == 0:
+        return None
+    kw = key_bytes // 8
+    o = out_dev.view(torch.int64).view(n, -1)
+    seen = torch.zeros(n, dtype=torch.bool, device=out_dev.device)
+    prev = None
+    for a in range(0, n, chunk):
+        b = min(n, a + chunk)
+        idx = o[a:b, kw]
+        if int(idx.min()) < 0 or int(idx.max()) >= n:
+            return "payload out of range"
+        if not torch.equal(inp_dev[idx], out_dev[a:b]):
+            return f"an output record in [{a}, {b}) differs from the input record its payload names"
+        seen[idx] = True
+        cols = [_ukey(o[a:b, w]) for w in reversed(range(kw))]   # most significant first
+        if prev is not None:
+            cols = [torch.cat([p, c]) for p, c in zip(prev, cols)]
+        gt = _lex_less([c[1:] for c in cols], [c[:-1] for c in cols])   # next key below this one
+        if bool(gt.any()):
+            j = int(torch.nonzero(gt)[0]) + a - (1 if prev is not None else 0)
+            return f"keys decrease at {j}"
+        prev = [c[-1:].clone() for c in cols]
+        del cols, gt
+    if not bool(seen.all()):
+        return "some input records are missing from the output"
+    return None

@@ -195,3 +195,23 @@ def test_prefix_search_validation(R):
     assert call(p, 100, p + G, p + 2 * G, 10, 16, 8, p + 3 * G, p + 3 * G + 40, 0, 0) == R.EINVAL   # lo and hi overlap
     assert call(p, 100, p + G, p + 2 * G, 10, 16, 8, p + 2 * G + 64, p + 4 * G, 0, 0) == R.EINVAL   # lo inside queries
     assert call(0, 0, 0, 0, 0, 16, 8, 0, 0, 0, 0) == R.OK                                           # no queries
+
+
+def test_inplace_validation_and_workspace(R):
+    f = R.sort_inplace_ptr
+    p = 1 << 20
+    assert f(p, 100, 6, 4, 0) == R.EUNSUPPORTED     # rec_bytes % 4
+    assert f(p, 100, 16, 0, 0) == R.EINVAL          # key_bytes == 0
+    assert f(p, 100, 8, 12, 0) == R.EINVAL          # key_bytes > rec_bytes
+    assert f(p, 100, 68, 8, 0) == R.EUNSUPPORTED    # rec_bytes > 64
+    assert f(0, 100, 16, 8, 0) == R.EINVAL          # null records
+    assert f(p + 4, 100, 16, 8, 0) == R.EINVAL      # misaligned
+    assert f(p, 1 << 40, 16, 8, 0) == R.EUNSUPPORTED
+    assert f(0, 1, 16, 8, 0) == R.OK                # n <= 1: nothing to do
+    assert f(0, 0, 16, 8, 0) == R.OK
+    # the workspace replaces tmp at a fraction of its size
+    n = 1 << 30
+    w = R.inplace_workspace_bytes(n, 16, 8)
+    assert 0 < w < n * 16 // 4
+    assert w < R.workspace_bytes(n, 16, 8)
+    assert R.inplace_workspace_bytes(n, 6, 4) == 0
