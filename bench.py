@@ -18,8 +18,10 @@ the CPU oracle baseline.
 Other legs: --batched (many independent arrays in one call vs one call per
 array), --kmer (k-mer counting: sort + duplicate removal with counts, at the
 sizes of the paper's three k-mer sets), --search (pattern-prefix search over
-a suffix array, naive vs sorted queries), --autotune (the autotuner's tuning
-for the workload's shape against the defaults).
+a suffix array, naive vs sorted queries), --inplace (the in-place variant,
+no second buffer, against the out-of-place sort on the same input),
+--autotune (the autotuner's tuning for the workload's shape against the
+defaults).
 """
 from __future__ import annotations
 
@@ -499,6 +501,125 @@ def search_main(args):
     print(json.dumps(out), flush=True)
 
 
+def inplace_main(args):
+    """The in-place sort (raduls_sort_inplace) of the default workload, timed
+    like the main leg, with per-phase rates, the roofline of the kernel with
+    the most time per step, its memory next to the out-of-place sort's, and
+    the out-of-place sort of the same input in the same run."""
+    import torch
+
+    import synth
+    from paper_1612_02557_amd import raduls
+    from synth import device as sdev
+    from tests.gpu_util import unstable_index_check
+
+    raduls.lib()
+    n = 1 << args.log2n
+    r, k = args.rec_bytes, args.key_bytes
+    if r < k + 8 or k not in (8, 16):
+        raise SystemExit("--inplace needs an 8- or 16-byte key followed by the 8-byte index payload")
+    spec = synth.Spec(n=n, rec_bytes=r, key_bytes=k, dist=args.dist, payload="index", seed=args.seed)
+    log(f"generating {n} x {r}-byte records ({args.dist}) on the device")
+    pristine = sdev.generate(spec)
+    rec = torch.empty_like(pristine)
+    torch.cuda.synchronize()
+    raduls.set_scheduler(raduls.SCHED_HEURISTIC)
+    raduls.set_tuning(None)
+    raduls.set_timing(2 if args.phases else 1)
+
+    def step(fn):
+        rec.copy_(pristine)
+        torch.cuda.synchronize()
+        fn()
+        torch.cuda.synchronize()
+        return raduls.get_stats().last_ms
+
+    for w in range(args.warmup):
+        log(f"warmup {w}: {step(lambda: raduls.sort_inplace(rec, k)):.3f} ms")
+    times, phase_acc = [], {}
+    for s_ in range(args.steps):
+        ms = step(lambda: raduls.sort_inplace(rec, k))
+        times.append(ms)
+        if args.phases:
+            for name, v in raduls.phase_times().items():
+                phase_acc.setdefault(name, []).append(v)
+        log(f"step {s_}: {ms:.3f} ms")
+    work = raduls.last_work()
+    ms_per_step = statistics.mean(times)
+    err = unstable_index_check(rec, pristine, k)
+    verified = err is None
+    if err:
+        log(f"VERIFICATION FAILED: {err}")
+    try:
+        raduls.sync_check()
+    except raduls.RadulsError as e:
+        log(f"device check failed: {e}")
+        verified = False
+
+    # algorithmic bytes: a level reads and writes its records twice (blocks
+    # by the classification, blocks moved by the permutation); finishing
+    # reads and writes once
+    passes = []
+    for l, (n_in, _moved) in enumerate(work["levels"]):
+        for kind, kern in (("hist", "k_ip_classify"), ("scatter", "k_ip_permute")):
+            name = f"L{l}.{kind}"
+            if name in phase_acc and n_in:
+                t = statistics.mean(phase_acc[name])
+                b = 2 * r * n_in
+                passes.append({"phase": name, "kernel": kern, "ms": t, "records": n_in, "alg_bytes": b,
+                               "GBps": b / t / 1e6 if t > 0 else None})
+    if "small_jobs" in phase_acc:
+        t = statistics.mean(phase_acc["small_jobs"])
+        b = 2 * r * work["wg_jobs"]
+        passes.append({"phase": "small_jobs", "kernel": "k_fin_jobs", "ms": t, "records": work["wg_jobs"],
+                       "alg_bytes": b, "GBps": b / t / 1e6 if t > 0 else None})
+    other = {nm: statistics.mean(v) for nm, v in phase_acc.items()
+             if not any(p_["phase"] == nm for p_ in passes)}
+    kernels = {}
+    for p_ in passes:
+        if not p_["ms"] or p_["records"] == 0:
+            continue
+        k_ = kernels.setdefault(p_["kernel"], {"launches": 0, "ms": 0.0, "alg_bytes": 0})
+        k_["launches"] += 1
+        k_["ms"] += p_["ms"]
+        k_["alg_bytes"] += p_["alg_bytes"]
+    for name, k_ in kernels.items():
+        k_["avg_launch_ms"] = k_["ms"] / k_["launches"]
+        k_["alg_bytes_per_launch"] = k_["alg_bytes"] / k_["launches"]
+        k_["GBps"] = k_["alg_bytes"] / k_["ms"] / 1e6
+    roof = None
+    if kernels:
+        dn, dom = max(kernels.items(), key=lambda kv: kv[1]["ms"])
+        wl = f"inplace-{args.dist}-2^{args.log2n}x{r}B"
+        roof = {"bound": "hbm", "achieved": dom["GBps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": dom["GBps"] / HBM_PEAK_GBPS, "traffic": load_traffic(dn, wl),
+                "kernel": dn, "launches_per_step": dom["launches"], "ms_per_step": dom["ms"],
+                "avg_launch_ms": dom["avg_launch_ms"], "alg_bytes_per_launch": dom["alg_bytes_per_launch"]}
+
+    # the out-of-place sort of the same input, for context
+    tmp = torch.empty_like(pristine)
+    oop = []
+    for s_ in range(max(1, args.steps)):
+        oop.append(step(lambda: raduls.sort(rec, k, tmp)))
+    del tmp
+    torch.cuda.empty_cache()
+    ms_oop = statistics.mean(oop)
+    mem = {"records_bytes": n * r, "inplace_workspace_bytes": raduls.inplace_workspace_bytes(n, r, k),
+           "out_of_place_extra_bytes": n * r + raduls.workspace_bytes(n, r, k)}
+    log(f"in place {ms_per_step:.2f} ms, out of place {ms_oop:.2f} ms; extra memory "
+        f"{mem['inplace_workspace_bytes'] / 2**30:.2f} GiB vs {mem['out_of_place_extra_bytes'] / 2**30:.2f} GiB")
+    out = {"metric": "records sorted per second in place (no second buffer), 16-byte records, 1 MI355X",
+           "value": n / (ms_per_step / 1e3), "unit": "records/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "u64" if k == 8 else "u128", "data": "synthetic",
+           "config": {"workload": f"in-place sort of 2^{args.log2n} {r}-byte records ({k}-byte {args.dist} keys, "
+                                  f"8-byte index payload; not stable)", "seed": args.seed},
+           "roofline": roof, "kernels": kernels, "passes": passes, "other_phases_ms": other,
+           "memory": mem, "out_of_place_ms": ms_oop, "inplace_over_out_of_place_time": ms_per_step / ms_oop,
+           "step_ms": times, "verified": verified}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -522,6 +643,7 @@ def main():
     ap.add_argument("--kmer", action="store_true", help="k-mer counting: sort + duplicate removal with counts")
     ap.add_argument("--kmer-sizes", default="63000000,413000000,1887000000")
     ap.add_argument("--search", action="store_true", help="batched pattern-prefix search over a suffix array")
+    ap.add_argument("--inplace", action="store_true", help="in-place sort (no second buffer) vs out of place")
     ap.add_argument("--text-log2", type=int, default=28)
     ap.add_argument("--q-log2", type=int, default=24)
     ap.add_argument("--autotune", action="store_true",
@@ -539,6 +661,8 @@ def main():
         return kmer_main(args)
     if args.search:
         return search_main(args)
+    if args.inplace:
+        return inplace_main(args)
 
     import torch
 

@@ -751,18 +751,37 @@ int make_inplace_plan(uint64_t n, uint32_t r, uint32_t k, int cus, Plan& p) {
   return RADULS_OK;
 }
 
-void enqueue_inplace(DeviceState& s, const Plan& p, void* records, hipStream_t st) {
+// Phase marks as for raduls_sort, read per level l as: 1+4l set-up,
+// 2+4l classification, 3+4l children, routing, ranges and cleanup, 4+4l
+// permutation; PH_SMALL tiny buckets, PH_JOBS finishing jobs.
+void enqueue_inplace(DeviceState& s, const Plan& p, void* records, hipStream_t st, bool phases) {
   const Work& w = s.work;
   const rd::IpWork& iw = s.ipw;
+  const int cus = s.cu_count;
+  PhaseMarks pm{&s, st, phases};
+  s.ph_id.clear();
+  pm.mark(-1);
   rd::launch_init(w, st);
   rd::launch_zero(iw.ctl, sizeof(rd::IpCtl), st);
   rd::launch_seed_single(p, w, st);
+  pm.mark(0);
   for (uint32_t l = 0; l < p.lmax; l++) {
     rd::launch_level_prep(p, w, l, st);
-    rd::launch_ip_level(p, w, iw, l, records, s.cu_count, st);
+    pm.mark(1 + 4 * l);
+    rd::launch_ip_classify(p, w, iw, l, records, cus, st);
+    pm.mark(2 + 4 * l);
+    rd::launch_ip_prepare(p, w, iw, l, records, cus, st);
+    pm.mark(3 + 4 * l);
+    rd::launch_ip_permute(p, w, iw, l, records, cus, st);
+    pm.mark(4 + 4 * l);
+    rd::launch_ip_cleanup(p, w, iw, l, records, cus, st);
+    pm.mark(3 + 4 * l);
   }
   rd::launch_small(p, w, records, records, st);
+  pm.mark(PH_SMALL);
   rd::launch_fin_jobs(p, w, records, records, st);
+  pm.mark(PH_JOBS);
+  s.ph_valid = phases;
 }
 
 }  // namespace
@@ -833,9 +852,7 @@ int raduls_sort_inplace(void* records, uint64_t n, uint32_t rec_bytes, uint32_t 
     if (!s.t0) { HIPCHK(hipEventCreate(&s.t0)); HIPCHK(hipEventCreate(&s.t1)); }
     HIPCHK(hipEventRecord(s.t0, st));
   }
-  s.ph_id.clear();
-  s.ph_valid = false;
-  enqueue_inplace(s, p, records, st);
+  enqueue_inplace(s, p, records, st, g_timing >= 2);
   s.last_plan = p;
   HIPCHK(hipGetLastError());
   if (g_timing) { HIPCHK(hipEventRecord(s.t1, st)); s.timed = true; }

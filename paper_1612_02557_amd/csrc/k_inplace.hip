@@ -805,16 +805,16 @@ __global__ __launch_bounds__(IP_WG) void k_ip_cleanup(Plan p, Work w, IpWork iw,
 
 // ---- launchers -------------------------------------------------------------------
 
-void launch_ip_level(const Plan& p, const Work& w, const IpWork& iw, uint32_t level, void* records, int cus,
-                     hipStream_t s) {
+// set-up, classification of the stripes, buckets of one workgroup
+void launch_ip_classify(const Plan& p, const Work& w, const IpWork& iw, uint32_t level, void* records, int cus,
+                        hipStream_t s) {
   uint8_t* rec = (uint8_t*)records;
   const size_t lds = (size_t)IP_R * IP_BLOCK_BYTES;
-  const uint32_t g1 = (uint32_t)cus;
   k_ip_setup<<<1, IP_WG, 0, s>>>(p, w, iw, level);
   switch (p.rw) {
 #define RD_CASE(n)                                                          \
   case n:                                                                   \
-    k_ip_classify<n><<<g1, IP_WG, lds, s>>>(p, w, iw, level, rec);          \
+    k_ip_classify<n><<<cus, IP_WG, lds, s>>>(p, w, iw, level, rec);         \
     k_ip_medium<n><<<iw.grid_medium, IP_WG, lds, s>>>(p, w, iw, level, rec); \
     break;
     RD_CASE(1) RD_CASE(2) RD_CASE(3) RD_CASE(4) RD_CASE(5) RD_CASE(6) RD_CASE(7) RD_CASE(8)
@@ -822,10 +822,16 @@ void launch_ip_level(const Plan& p, const Work& w, const IpWork& iw, uint32_t le
 #undef RD_CASE
     default: break;
   }
-  k_ip_bucket<<<g1, IP_WG, 0, s>>>(p, w, iw, level);
+}
+
+// children of the large buckets, routing, child ranges, permutation chunks
+void launch_ip_prepare(const Plan& p, const Work& w, const IpWork& iw, uint32_t level, void* records, int cus,
+                       hipStream_t s) {
+  uint8_t* rec = (uint8_t*)records;
+  k_ip_bucket<<<cus, IP_WG, 0, s>>>(p, w, iw, level);
   launch_level_scan(p, w, level, s);
   switch (p.rw) {
-#define RD_CASE(n) case n: k_ip_ranges<n><<<2 * g1, IP_WG, 0, s>>>(p, w, iw, level, rec); break;
+#define RD_CASE(n) case n: k_ip_ranges<n><<<2 * cus, IP_WG, 0, s>>>(p, w, iw, level, rec); break;
     RD_CASE(1) RD_CASE(2) RD_CASE(3) RD_CASE(4) RD_CASE(5) RD_CASE(6) RD_CASE(7) RD_CASE(8)
     RD_CASE(9) RD_CASE(10) RD_CASE(11) RD_CASE(12) RD_CASE(13) RD_CASE(14) RD_CASE(15) RD_CASE(16)
 #undef RD_CASE
@@ -833,12 +839,25 @@ void launch_ip_level(const Plan& p, const Work& w, const IpWork& iw, uint32_t le
   }
   k_ip_chunks<<<1, IP_WG, 0, s>>>(iw);
   launch_zero(iw.done, (size_t)((iw.done_words + 1) / 2) * 8, s);
+}
+
+void launch_ip_permute(const Plan& p, const Work& w, const IpWork& iw, uint32_t level, void* records, int cus,
+                       hipStream_t s) {
+  uint8_t* rec = (uint8_t*)records;
   switch (p.rw) {
-#define RD_CASE(n)                                                                   \
-  case n:                                                                            \
-    k_ip_permute<n><<<8 * g1, IP_PERM_WG, 0, s>>>(p, w, iw, level, rec);             \
-    k_ip_cleanup<n><<<4 * g1, IP_WG, 0, s>>>(p, w, iw, level, rec);                  \
-    break;
+#define RD_CASE(n) case n: k_ip_permute<n><<<8 * cus, IP_PERM_WG, 0, s>>>(p, w, iw, level, rec); break;
+    RD_CASE(1) RD_CASE(2) RD_CASE(3) RD_CASE(4) RD_CASE(5) RD_CASE(6) RD_CASE(7) RD_CASE(8)
+    RD_CASE(9) RD_CASE(10) RD_CASE(11) RD_CASE(12) RD_CASE(13) RD_CASE(14) RD_CASE(15) RD_CASE(16)
+#undef RD_CASE
+    default: break;
+  }
+}
+
+void launch_ip_cleanup(const Plan& p, const Work& w, const IpWork& iw, uint32_t level, void* records, int cus,
+                       hipStream_t s) {
+  uint8_t* rec = (uint8_t*)records;
+  switch (p.rw) {
+#define RD_CASE(n) case n: k_ip_cleanup<n><<<4 * cus, IP_WG, 0, s>>>(p, w, iw, level, rec); break;
     RD_CASE(1) RD_CASE(2) RD_CASE(3) RD_CASE(4) RD_CASE(5) RD_CASE(6) RD_CASE(7) RD_CASE(8)
     RD_CASE(9) RD_CASE(10) RD_CASE(11) RD_CASE(12) RD_CASE(13) RD_CASE(14) RD_CASE(15) RD_CASE(16)
 #undef RD_CASE

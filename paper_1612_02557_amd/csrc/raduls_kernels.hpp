@@ -23,9 +23,16 @@ void launch_small(const Plan& p, const Work& w, void* records, void* tmp, hipStr
 void launch_small_jobs(const Plan& p, const Work& w, void* records, void* tmp, hipStream_t s);
 void launch_fin_jobs(const Plan& p, const Work& w, void* records, void* tmp, hipStream_t s);
 void launch_copy(const Plan& p, const Work& w, void* records, const void* tmp, hipStream_t s);
-// one in-place level (k_inplace.hip): classification, routing, permutation, cleanup
-void launch_ip_level(const Plan& p, const Work& w, const IpWork& iw, uint32_t level, void* records, int cus,
-                     hipStream_t s);
+// one in-place level (k_inplace.hip), in this order: set-up and
+// classification; children, routing, ranges; permutation; cleanup
+void launch_ip_classify(const Plan& p, const Work& w, const IpWork& iw, uint32_t level, void* records, int cus,
+                        hipStream_t s);
+void launch_ip_prepare(const Plan& p, const Work& w, const IpWork& iw, uint32_t level, void* records, int cus,
+                       hipStream_t s);
+void launch_ip_permute(const Plan& p, const Work& w, const IpWork& iw, uint32_t level, void* records, int cus,
+                       hipStream_t s);
+void launch_ip_cleanup(const Plan& p, const Work& w, const IpWork& iw, uint32_t level, void* records, int cus,
+                       hipStream_t s);
 
 // runs of equal keys in key-ordered records (k_count.hip); the workspace
 // holds the control block and the look-back words
