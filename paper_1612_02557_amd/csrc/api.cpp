@@ -667,7 +667,7 @@ IpLayout ip_layout_of(uint64_t n, uint32_t rw, uint64_t cap_big, uint32_t grid_m
   L.lcnt = take(L.cap_stripes * rd::IP_R * 2);
   L.side = take(L.cap_stripes * rd::IP_R * rd::IP_BLOCK_BYTES);
   L.prot = take(L.cap_ranges * rd::IP_BLOCK_BYTES);
-  L.W = take(L.cap_ranges * 8);
+  L.W = take(L.cap_ranges * rd::IP_WSTRIDE * 8);
   L.rbase = take(L.cap_ranges * 8);
   L.rlim = take(L.cap_ranges * 8);
   L.rf = take(L.cap_ranges * 4);

@@ -169,7 +169,7 @@ __device__ __forceinline__ uint32_t blk_digit(Blk x, const KeyFmt& kf, Dig g) {
   uint64_t hi = 0;
   if constexpr (RW > 2) hi = (uint32_t)__shfl((int)x.a, 2);
   if constexpr (RW > 3) hi |= (uint64_t)(uint32_t)__shfl((int)x.a, 3) << 32;
-  return key_digit(Key{lo & kf.mlo, hi & kf.mhi}, g.shift, g.mask, kf);
+  return __builtin_amdgcn_readfirstlane(key_digit(Key{lo & kf.mlo, hi & kf.mhi}, g.shift, g.mask, kf));
 }
 
 // Child ranges of one bucket: cursors, first slot, blocks and end (records
@@ -694,7 +694,7 @@ __global__ __launch_bounds__(IP_WG) void k_ip_ranges(Plan p, Work w, IpWork iw, 
       blk_store(recw + (uint64_t)hslot * WB, x, WB, lane);
     }
     if (t == 0) {
-      iw.W[r] = ((uint64_t)f << 32) | (uint64_t)(cut + IP_BIAS);
+      iw.W[(uint64_t)r * IP_WSTRIDE] = ((uint64_t)f << 32) | (uint64_t)(cut + IP_BIAS);
       iw.rinit[r] = cut;
       iw.chunk_start[r] = (Fr + IP_CHUNK - 1) / IP_CHUNK;
     }
@@ -734,29 +734,188 @@ __global__ __launch_bounds__(IP_WG) void k_ip_chunks(IpWork iw) {
   }
 }
 
+// Permutation of the large buckets' blocks.  A wavefront runs IP_CHAINS
+// chains at once, each carrying one block (the same steps as ip_drain): per
+// round every chain issues its cursor claim -- a read claim on the wave's
+// current range if it holds no block, a write claim on its block's digit
+// otherwise -- then the block loads the claims call for, so that the
+// latencies of the chains overlap.  Read bits are set before any chain of
+// the round waits on one (a chain may wait on a slot that another chain of
+// the same wave has just read).
+constexpr uint32_t IP_CHAINS = 4;
+static_assert(IP_CHAINS <= 32, "the slots of one read claim span at most two bit words");
+
 template <int RW>
 __global__ __launch_bounds__(IP_PERM_WG) void k_ip_permute(Plan p, Work w, IpWork iw, uint32_t level, uint8_t* rec) {
   const uint32_t nch = iw.ctl->nchunks, stride = iw.ctl->stride, nr = iw.ctl->nranges;
   const KeyFmt kf = make_keyfmt(p.key_bytes);
-  const uint32_t B = ip_block_records(RW);
+  const uint32_t B = ip_block_records(RW), WB = B * RW;
   const Bucket* list = ip_list(p, w, level);
   const uint32_t lane = lane_id();
+  constexpr uint32_t NC = IP_CHAINS;
+  constexpr uint64_t RB = 4 * RW;
+  // the wave's current chunk: range ri of large bucket rlb (first record
+  // rP, rcount records, digit rg), `quota` reads left
+  uint32_t quota = 0, rlb = 0, ri = 0;
+  uint64_t rP = 0, rcount = 0;
+  Dig rg{0u, 0u};
+  bool more = true;
+  // chains: block x of digit v of large bucket lb; slot of this round; end
+  // of the block's child
+  Blk x[NC], y[NC];
+  uint32_t v[NC], lbc[NC], slot[NC], mode[NC];
+  uint64_t lim[NC];
+  bool has[NC];
+#pragma unroll
+  for (uint32_t c = 0; c < NC; c++) {
+    has[c] = false;
+    v[c] = lbc[c] = slot[c] = mode[c] = 0;
+    lim[c] = 0;
+    x[c] = y[c] = Blk{0u, 0u};
+  }
+  enum : uint32_t { NONE = 0, READ = 1, SWAP = 2, PLACE = 3 };
   for (;;) {
-    uint32_t c = 0;
-    if (lane == 0) c = atomicAdd(&iw.ctl->chunk_ticket, 1u);
-    c = __builtin_amdgcn_readfirstlane(__shfl(c, 0));
-    if (c >= nch) break;
-    const uint32_t cp = (uint32_t)(((uint64_t)c * stride) % nch);
-    const uint32_t r = last_le(iw.chunk_start, nr, cp);
-    const uint32_t lb = r / IP_R, i = r - lb * IP_R;
-    const Bucket Bk = list[iw.large[lb]];
-    const Dig g = bucket_digit(p, kf, Bk.bit);
-    const uint64_t o = (uint64_t)lb * IP_R;
-    const Ranges rg{iw.W + o, iw.rinit + o, iw.rf + o, iw.rF + o, iw.rlim + o};
-    uint32_t* recw = reinterpret_cast<uint32_t*>(rec + Bk.begin * (uint64_t)(4 * RW));
-    uint32_t* protw0 = reinterpret_cast<uint32_t*>(iw.prot + o * IP_BLOCK_BYTES);
-    ip_drain<RW>(rg, i, IP_CHUNK, recw, Bk.count, B, g, kf, iw.done, Bk.begin / B, protw0, p.spin_limit,
-                 &iw.ctl->error);
+    bool need = false, busy = false;
+#pragma unroll
+    for (uint32_t c = 0; c < NC; c++) {
+      need = need || !has[c];
+      busy = busy || has[c];
+    }
+    if (need && quota == 0 && more) {
+      uint32_t t = 0;
+      if (lane == 0) t = atomicAdd(&iw.ctl->chunk_ticket, 1u);
+      t = __builtin_amdgcn_readfirstlane(__shfl(t, 0));
+      if (t >= nch) {
+        more = false;
+      } else {
+        const uint32_t cp = (uint32_t)(((uint64_t)t * stride) % nch);
+        const uint32_t r = last_le(iw.chunk_start, nr, cp);
+        rlb = r / IP_R;
+        ri = r - rlb * IP_R;
+        quota = IP_CHUNK;
+        const Bucket Bk = list[iw.large[rlb]];
+        rP = Bk.begin;
+        rcount = Bk.count;
+        rg = bucket_digit(p, kf, Bk.bit);
+      }
+    }
+    if (!busy && quota == 0 && !more) break;
+    // claims: the chains without a block share one read claim of up to
+    // their number of slots; the others claim a write slot each
+    uint32_t nneed = 0;
+#pragma unroll
+    for (uint32_t c = 0; c < NC; c++) nneed += has[c] ? 0u : 1u;
+    nneed = min(nneed, quota);
+    uint64_t rold = 0;
+    if (nneed && lane == 0)
+      rold = atomicAdd((unsigned long long*)&iw.W[((uint64_t)rlb * IP_R + ri) * IP_WSTRIDE], 0ull - nneed);
+    uint64_t old[NC];
+#pragma unroll
+    for (uint32_t c = 0; c < NC; c++) {
+      old[c] = 0;
+      mode[c] = NONE;
+      if (has[c]) {
+        mode[c] = SWAP;
+        if (lane == 0)
+          old[c] = atomicAdd((unsigned long long*)&iw.W[((uint64_t)lbc[c] * IP_R + v[c]) * IP_WSTRIDE], 1ull << 32);
+      }
+    }
+    // read slots rc - 1, rc - 2, ... down to the write cursor
+    uint32_t rfirst = 0, ngot = 0;
+    if (nneed) {
+      quota -= nneed;
+      const uint64_t o = bcast64(__shfl((unsigned long long)rold, 0));
+      const int64_t wc = (int64_t)(o >> 32), rc = (int64_t)(uint32_t)o - (int64_t)IP_BIAS;
+      const int64_t avail = rc - wc;
+      ngot = avail <= 0 ? 0u : (uint32_t)min<int64_t>(avail, nneed);
+      if (ngot < nneed) quota = 0;  // range exhausted: the rest of the chunk is void
+      rfirst = (uint32_t)(rc - (int64_t)ngot);  // lowest slot read
+      if (ngot && (uint64_t)rc > (rcount + B - 1) / B) {  // cannot happen
+        if (lane == 0) atomicOr(&iw.ctl->error, 4u);
+        ngot = 0;
+        quota = 0;
+      }
+    }
+    // decode, loads
+    uint32_t k = 0;
+#pragma unroll
+    for (uint32_t c = 0; c < NC; c++) {
+      if (!has[c] && k < ngot) {
+        mode[c] = READ;
+        lbc[c] = rlb;
+        slot[c] = rfirst + k;
+        x[c] = blk_load(reinterpret_cast<const uint32_t*>(rec + rP * RB) + (uint64_t)slot[c] * WB, WB, lane);
+        k++;
+      }
+      if (mode[c] != SWAP) continue;
+      // (a write cursor past its child's blocks cannot happen; the cleanup
+      // checks every final cursor, and a slot past the bucket is refused)
+      const uint64_t o = bcast64(__shfl((unsigned long long)old[c], 0));
+      const int64_t rc = (int64_t)(uint32_t)o - (int64_t)IP_BIAS;
+      const uint32_t ws = (uint32_t)(o >> 32);
+      const Bucket Bk = list[iw.large[lbc[c]]];
+      if (ws >= (Bk.count + B - 1) / B) {
+        if (lane == 0) atomicOr(&iw.ctl->error, 4u);
+        mode[c] = NONE;
+        has[c] = false;
+        continue;
+      }
+      slot[c] = ws;
+      lim[c] = uniform64(iw.rlim[(uint64_t)lbc[c] * IP_R + v[c]]);
+      if ((int64_t)ws < rc) y[c] = blk_load(reinterpret_cast<const uint32_t*>(rec + Bk.begin * RB) + (uint64_t)ws * WB, WB, lane);
+      else mode[c] = PLACE;
+    }
+    wait_loads();
+    // read bits first (the slots read are consecutive: at most two words)
+    if (ngot && lane == 0) {
+      const uint64_t b0 = rP / B + rfirst, b1 = b0 + ngot - 1;
+      const uint32_t lo = (uint32_t)(b0 & 31), hi = (uint32_t)(b1 & 31);
+      if ((b0 >> 5) == (b1 >> 5)) {
+        atomicOr(&iw.done[b0 >> 5], (0xFFFFFFFFu >> (31 - hi)) & (0xFFFFFFFFu << lo));
+      } else {
+        atomicOr(&iw.done[b0 >> 5], 0xFFFFFFFFu << lo);
+        atomicOr(&iw.done[b1 >> 5], 0xFFFFFFFFu >> (31 - hi));
+      }
+    }
+#pragma unroll
+    for (uint32_t c = 0; c < NC; c++) {
+      if (mode[c] != READ) continue;
+      v[c] = blk_digit<RW>(x[c], kf, rg);
+      has[c] = true;
+    }
+    // then the writes
+#pragma unroll
+    for (uint32_t c = 0; c < NC; c++) {
+      if (mode[c] != SWAP && mode[c] != PLACE) continue;
+      const uint64_t ro = (uint64_t)lbc[c] * IP_R + v[c];
+      const Bucket Bk = list[iw.large[lbc[c]]];
+      uint32_t* recw = reinterpret_cast<uint32_t*>(rec + Bk.begin * RB);
+      uint32_t* protw = reinterpret_cast<uint32_t*>(iw.prot + ro * IP_BLOCK_BYTES);
+      const uint32_t ws = slot[c];
+      if (mode[c] == PLACE && ws < iw.rinit[ro]) {
+        // the slot's block was claimed by a reader: wait until it has it
+        const uint64_t bi = Bk.begin / B + ws;
+        uint32_t spins = 0;
+        for (;;) {
+          uint32_t word = 0;
+          if (lane == 0) word = __hip_atomic_load(&iw.done[bi >> 5], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          word = __builtin_amdgcn_readfirstlane(__shfl(word, 0));
+          if ((word >> (bi & 31)) & 1u) break;
+          if (++spins > p.spin_limit) {
+            if (lane == 0) atomicOr(&iw.ctl->error, 2u);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+      }
+      put_block<RW>(x[c], recw, Bk.count, ws, B, lim[c], protw, lane);
+      if (mode[c] == SWAP) {
+        x[c] = y[c];
+        v[c] = blk_digit<RW>(y[c], kf, bucket_digit(p, kf, Bk.bit));
+      } else {
+        has[c] = false;
+      }
+    }
   }
 }
 
@@ -784,7 +943,9 @@ __global__ __launch_bounds__(IP_WG) void k_ip_cleanup(Plan p, Work w, IpWork iw,
     const uint64_t tail0 = F ? min(E, lim) : lim;
     const uint64_t nh = (head_end - b0) + (lim - tail0);
     const uint64_t pc = F && E > lim ? E - lim : 0;
-    if (t == 0 && nh != L + pc) atomicOr(&iw.ctl->error, 4u);
+    // every block of the child was written: its write cursor ends at f + F
+    if (t == 0 && (nh != L + pc || (uint32_t)(iw.W[(uint64_t)r * IP_WSTRIDE] >> 32) != f + F))
+      atomicOr(&iw.ctl->error, 4u);
     const uint8_t* pr = iw.prot + (uint64_t)r * IP_BLOCK_BYTES;
     for (uint64_t k = t; k < nh; k += IP_WG) {
       const uint64_t dst = k < head_end - b0 ? b0 + k : tail0 + (k - (head_end - b0));

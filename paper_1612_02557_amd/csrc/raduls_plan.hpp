@@ -151,8 +151,9 @@ constexpr uint32_t IP_R = 256;            // digits of a level (8 bits)
 constexpr uint32_t IP_BLOCK_BYTES = 512;  // bytes of a block, at most
 constexpr uint32_t IP_SLB = 32768;        // blocks per stripe; a bucket of at most one stripe is one workgroup's
 constexpr uint32_t IP_MAX_STRIPES = 8192; // stripes of one bucket, at most
-constexpr uint32_t IP_CHUNK = 16;         // block reads per claim of the permutation
+constexpr uint32_t IP_CHUNK = 64;         // block reads per claim of the permutation
 constexpr uint32_t IP_BIAS = 1u << 30;    // added to the read cursor so that extra decrements never borrow
+constexpr uint32_t IP_WSTRIDE = 16;       // 64-bit words between the cursor words of two ranges (one per cache line)
 __host__ __device__ constexpr uint32_t ip_block_records(uint32_t rw) { return IP_BLOCK_BYTES / (4 * rw); }
 
 struct IpCtl {
@@ -174,7 +175,7 @@ struct IpWork {
   uint16_t* lcnt;          // cap_stripes x IP_R: records left over per stripe and digit
   uint8_t* side;           // cap_stripes x IP_R x IP_BLOCK_BYTES: those records
   uint8_t* prot;           // cap_ranges x IP_BLOCK_BYTES: records of a child's last block past the child's end
-  uint64_t* W;             // cap_ranges: write cursor << 32 | (read cursor + IP_BIAS), in block slots
+  uint64_t* W;             // cap_ranges x IP_WSTRIDE: write cursor << 32 | (read cursor + IP_BIAS), in block slots
   uint64_t* rbase;         // cap_ranges: first record of each child, relative to its bucket
   uint64_t* rlim;          // cap_ranges: end of each child, relative to its bucket
   uint32_t* rf;            // cap_ranges: first block slot starting inside the child
