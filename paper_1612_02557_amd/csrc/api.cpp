@@ -642,7 +642,7 @@ uint32_t ip_slb() {
 
 struct IpLayout {
   size_t ctl, large, stripe_first, medium, nbfull, lcnt, side, prot, W, rbase, rlim, rf, re, rF, rL, rinit,
-      chunk_start, done, mscratch, total;
+      chunk_start, done, bdig, mscratch, total;
   uint64_t cap_large, cap_stripes, cap_ranges, done_words;
 };
 
@@ -677,6 +677,7 @@ IpLayout ip_layout_of(uint64_t n, uint32_t rw, uint64_t cap_big, uint32_t grid_m
   L.rinit = take(L.cap_ranges * 4);
   L.chunk_start = take((L.cap_ranges + 1) * 4);
   L.done = take(L.done_words * 4 + 8);
+  L.bdig = take(L.done_words * 32);
   L.mscratch = take((size_t)grid_medium * rd::IP_R * rd::IP_BLOCK_BYTES);
   L.total = o;
   return L;
@@ -721,6 +722,7 @@ int ensure_ip_workspace(DeviceState& s, const Plan& p) {
   w.rinit = (uint32_t*)(b + L.rinit);
   w.chunk_start = (uint32_t*)(b + L.chunk_start);
   w.done = (uint32_t*)(b + L.done);
+  w.bdig = b + L.bdig;
   w.mscratch = b + L.mscratch;
   w.cap_large = L.cap_large;
   w.cap_stripes = L.cap_stripes;

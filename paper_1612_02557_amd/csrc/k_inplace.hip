@@ -204,66 +204,121 @@ __device__ __forceinline__ void put_block(Blk x, uint32_t* recw, uint64_t count,
   }
 }
 
-// One wavefront takes up to `quota` unread blocks from range i (from its
-// read cursor down) and carries each to its digit's write cursor, taking
-// out and carrying on what it finds there if that slot is still unread.
-// `done` bits (index bit0 + slot) mark slots whose reader has its block.
+// One wavefront moves blocks of the workgroup's own bucket (cursors and
+// bits in LDS) with four chains at a time.  A chain without a block takes
+// one from the back of a range (reads come from ranges first, first + step,
+// ... each until it is exhausted); a chain with a block of digit v claims
+// v's write slot: a slot still below v's read cursor holds an unread block,
+// which is taken out first and carried on; a slot claimed by a reader is
+// waited for through its bit (bounded).  Per round all chains' claims and
+// block loads are issued before any is waited for, and read bits are set
+// before any chain waits on one.
 template <int RW>
-__device__ void ip_drain(const Ranges& rg, uint32_t i, uint32_t quota, uint32_t* recw, uint64_t count, uint32_t B,
-                         Dig g, const KeyFmt& kf, uint32_t* done, uint64_t bit0, uint32_t* protw0,
-                         uint32_t spin_limit, uint32_t* err) {
+__device__ void ip_drain_multi(const Ranges& rg, uint32_t first, uint32_t step, uint32_t* recw, uint64_t count,
+                               uint32_t B, Dig g, const KeyFmt& kf, uint32_t* done, uint32_t* protw0,
+                               uint32_t spin_limit, uint32_t* err) {
+  constexpr uint32_t NC = 4;
   const uint32_t lane = lane_id();
   const uint32_t WB = B * RW;
-  const uint32_t PW = IP_BLOCK_BYTES / 4;  // words of a child's aside area
-  const uint64_t nblk = (count + B - 1) / B;  // block slots of the bucket
-  for (uint32_t k = 0; k < quota; k++) {
-    uint64_t old = 0;
-    if (lane == 0) old = atomicAdd((unsigned long long*)&rg.W[i], ~0ull);  // read cursor - 1
-    old = bcast64(__shfl((unsigned long long)old, 0));
-    // failed claims may take the read cursor a little below the range's
-    // first slot: compare signed
-    const int64_t wc = (int64_t)(old >> 32), rc = (int64_t)(uint32_t)old - (int64_t)IP_BIAS;
-    if (rc <= wc) break;  // every block of the range is taken
-    const uint32_t rs = (uint32_t)(rc - 1);
-    if (rs >= nblk) {  // cannot happen: the cursors start inside the bucket
-      if (lane == 0) atomicOr(err, 4u);
-      return;
+  const uint32_t PW = IP_BLOCK_BYTES / 4;
+  const uint64_t nblk = (count + B - 1) / B;
+  uint32_t ri = first;
+  bool more = ri < IP_R;
+  Blk x[NC], y[NC];
+  uint32_t v[NC], slot[NC], mode[NC];
+  uint64_t lim[NC];
+  bool has[NC];
+#pragma unroll
+  for (uint32_t c = 0; c < NC; c++) {
+    has[c] = false;
+    v[c] = slot[c] = mode[c] = 0;
+    lim[c] = 0;
+    x[c] = y[c] = Blk{0u, 0u};
+  }
+  enum : uint32_t { NONE = 0, READ = 1, SWAP = 2, PLACE = 3 };
+  for (;;) {
+    uint32_t nneed = 0;
+    bool busy = false;
+#pragma unroll
+    for (uint32_t c = 0; c < NC; c++) {
+      nneed += has[c] ? 0u : 1u;
+      busy = busy || has[c];
     }
-    Blk x = blk_load(recw + (uint64_t)rs * WB, WB, lane);
-    wait_loads();
-    if (lane == 0) {
-      const uint64_t bi = bit0 + rs;
-      atomicOr(&done[bi >> 5], 1u << (bi & 31));
-    }
-    uint32_t v = blk_digit<RW>(x, kf, g);
-    for (;;) {
-      uint64_t o2 = 0;
-      if (lane == 0) o2 = atomicAdd((unsigned long long*)&rg.W[v], 1ull << 32);
-      o2 = bcast64(__shfl((unsigned long long)o2, 0));
-      const uint32_t ws = (uint32_t)(o2 >> 32);
-      const int64_t rr = (int64_t)(uint32_t)o2 - (int64_t)IP_BIAS;
-      if (ws >= rg.f[v] + rg.F[v] || ws >= nblk) {  // more blocks of this digit than its child holds: refuse
-        if (lane == 0) atomicOr(err, 4u);
-        return;
+    if (!busy && !more) break;
+    if (!more) nneed = 0;
+    uint64_t rold = 0;
+    if (nneed && lane == 0) rold = atomicAdd((unsigned long long*)&rg.W[ri], 0ull - nneed);
+    uint64_t old[NC];
+#pragma unroll
+    for (uint32_t c = 0; c < NC; c++) {
+      old[c] = 0;
+      mode[c] = NONE;
+      if (has[c]) {
+        mode[c] = SWAP;
+        if (lane == 0) old[c] = atomicAdd((unsigned long long*)&rg.W[v[c]], 1ull << 32);
       }
-      if ((int64_t)ws < rr) {
-        // slot ws still holds an unread block: take it out, then put ours
-        const Blk y = blk_load(recw + (uint64_t)ws * WB, WB, lane);
-        wait_loads();
-        put_block<RW>(x, recw, count, ws, B, rg.lim[v], protw0 + v * PW, lane);
-        x = y;
-        v = blk_digit<RW>(y, kf, g);
+    }
+    uint32_t rfirst = 0, ngot = 0;
+    if (nneed) {
+      const uint64_t o = bcast64(__shfl((unsigned long long)rold, 0));
+      const int64_t wc = (int64_t)(o >> 32), rc = (int64_t)(uint32_t)o - (int64_t)IP_BIAS;
+      const int64_t avail = rc - wc;
+      ngot = avail <= 0 ? 0u : (uint32_t)min<int64_t>(avail, nneed);
+      rfirst = (uint32_t)(rc - (int64_t)ngot);
+      if (ngot && (uint64_t)rc > nblk) {  // cannot happen
+        if (lane == 0) atomicOr(err, 4u);
+        ngot = 0;
+      }
+      if (ngot < nneed) {  // range exhausted: the next one
+        ri += step;
+        more = ri < IP_R;
+      }
+    }
+    uint32_t k = 0;
+#pragma unroll
+    for (uint32_t c = 0; c < NC; c++) {
+      if (!has[c] && k < ngot) {
+        mode[c] = READ;
+        slot[c] = rfirst + k;
+        x[c] = blk_load(recw + (uint64_t)slot[c] * WB, WB, lane);
+        k++;
+      }
+      if (mode[c] != SWAP) continue;
+      const uint64_t o = bcast64(__shfl((unsigned long long)old[c], 0));
+      const int64_t rc = (int64_t)(uint32_t)o - (int64_t)IP_BIAS;
+      const uint32_t ws = (uint32_t)(o >> 32);
+      if (ws >= rg.f[v[c]] + rg.F[v[c]] || ws >= nblk) {  // cannot happen: drop the block, report
+        if (lane == 0) atomicOr(err, 4u);
+        mode[c] = NONE;
+        has[c] = false;
         continue;
       }
-      if (ws < rg.rinit[v]) {
-        // the slot's block was claimed by a reader: wait until it has it
-        const uint64_t bi = bit0 + ws;
+      slot[c] = ws;
+      lim[c] = rg.lim[v[c]];
+      if ((int64_t)ws < rc) y[c] = blk_load(recw + (uint64_t)ws * WB, WB, lane);
+      else mode[c] = PLACE;
+    }
+    wait_loads();
+    if (ngot && lane == 0) {
+      for (uint32_t j = 0; j < ngot; j++) atomicOr(&done[(rfirst + j) >> 5], 1u << ((rfirst + j) & 31));
+    }
+#pragma unroll
+    for (uint32_t c = 0; c < NC; c++) {
+      if (mode[c] != READ) continue;
+      v[c] = blk_digit<RW>(x[c], kf, g);
+      has[c] = true;
+    }
+#pragma unroll
+    for (uint32_t c = 0; c < NC; c++) {
+      if (mode[c] != SWAP && mode[c] != PLACE) continue;
+      const uint32_t ws = slot[c];
+      if (mode[c] == PLACE && ws < rg.rinit[v[c]]) {
         uint32_t spins = 0;
         for (;;) {
           uint32_t word = 0;
-          if (lane == 0) word = __hip_atomic_load(&done[bi >> 5], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (lane == 0) word = __hip_atomic_load(&done[ws >> 5], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           word = __builtin_amdgcn_readfirstlane(__shfl(word, 0));
-          if ((word >> (bi & 31)) & 1u) break;
+          if ((word >> (ws & 31)) & 1u) break;
           if (++spins > spin_limit) {
             if (lane == 0) atomicOr(err, 2u);
             break;
@@ -271,8 +326,13 @@ __device__ void ip_drain(const Ranges& rg, uint32_t i, uint32_t quota, uint32_t*
           __builtin_amdgcn_s_sleep(1);
         }
       }
-      put_block<RW>(x, recw, count, ws, B, rg.lim[v], protw0 + v * PW, lane);
-      break;
+      put_block<RW>(x[c], recw, count, ws, B, lim[c], protw0 + v[c] * PW, lane);
+      if (mode[c] == SWAP) {
+        x[c] = y[c];
+        v[c] = blk_digit<RW>(y[c], kf, g);
+      } else {
+        has[c] = false;
+      }
     }
   }
 }
@@ -297,7 +357,7 @@ struct IpCls {
 // v * B).  OR of every key XOR a key of the bucket into vlo/vhi.
 template <int RW>
 __device__ void classify(uint8_t* rec, uint64_t P, uint64_t s0, uint64_t s1, Dig g, const KeyFmt& kf, uint32_t B,
-                         uint32_t* buf, IpCls& S, uint64_t& vlo, uint64_t& vhi) {
+                         uint32_t* buf, IpCls& S, uint64_t& vlo, uint64_t& vhi, uint8_t* bdig) {
   const uint32_t t = threadIdx.x;
   constexpr uint32_t IP_IPT = RW > 8 ? 2 : 4;  // records per thread of a tile
   constexpr uint32_t TILE = IP_IPT * IP_WG;
@@ -321,13 +381,24 @@ __device__ void classify(uint8_t* rec, uint64_t P, uint64_t s0, uint64_t s1, Dig
 #pragma unroll
     for (uint32_t u = 0; u < IP_IPT; u++) {
       const uint64_t i = t0 + u * IP_WG + t;
+      const bool ok = i < s1;
       v[u] = 0;
       q[u] = 0;
-      if (i < s1) {
+      if (ok) {
         const Key k = rec_key<RW>(r[u], kf);
         vlo |= k.lo ^ ref.lo;
         vhi |= k.hi ^ ref.hi;
         v[u] = key_digit(k, g.shift, g.mask, kf);
+      }
+      // a wave whose records share one digit (runs of equal keys) takes its
+      // ranks with one atomic instead of 64 on the same counter
+      const uint64_t act = __ballot(ok);
+      const uint32_t v0 = __shfl(v[u], 0);
+      if (act == ~0ull && __ballot(v[u] == v0) == ~0ull) {
+        uint32_t base = 0;
+        if (lane_id() == 0) base = atomicAdd(&S.cnt[v0], 64u);
+        q[u] = (uint32_t)__shfl(base, 0) + lane_id();
+      } else if (ok) {
         q[u] = atomicAdd(&S.cnt[v[u]], 1u);
       }
     }
@@ -350,6 +421,9 @@ __device__ void classify(uint8_t* rec, uint64_t P, uint64_t s0, uint64_t s1, Dig
       S.nbv[t] = nb;
       S.tot[t] += c;
       S.cnt[t] = 0;
+      // each block's digit, by its index from the stripe's first block
+      if (bdig)
+        for (uint32_t q = 0; q < nb; q++) bdig[wp + ex + q] = (uint8_t)t;
     }
     __syncthreads();
     if (t == 0) S.wpos = wp + total;
@@ -491,7 +565,7 @@ __global__ __launch_bounds__(IP_WG) void k_ip_classify(Plan p, Work w, IpWork iw
     const uint64_t s1 = min(Bk.count, s0 + SL);
     const Dig g = bucket_digit(p, kf, Bk.bit);
     uint64_t vlo = 0, vhi = 0;
-    classify<RW>(rec, Bk.begin, s0, s1, g, kf, B, buf, S, vlo, vhi);
+    classify<RW>(rec, Bk.begin, s0, s1, g, kf, B, buf, S, vlo, vhi, iw.bdig + Bk.begin / B + s0 / B);
     // leftovers aside, counts to the bucket's histogram
     uint8_t* side = iw.side + (uint64_t)s * IP_R * IP_BLOCK_BYTES;
     for (uint32_t idx = t; idx < IP_R * B; idx += IP_WG) {
@@ -540,7 +614,7 @@ __global__ __launch_bounds__(IP_WG) void k_ip_medium(Plan p, Work w, IpWork iw, 
     const uint64_t P = Bk.begin, count = Bk.count;
     const Dig g = bucket_digit(p, kf, Bk.bit);
     uint64_t vlo = 0, vhi = 0;
-    classify<RW>(rec, P, 0, count, g, kf, B, buf, S, vlo, vhi);
+    classify<RW>(rec, P, 0, count, g, kf, B, buf, S, vlo, vhi, nullptr);
     or_vary(w, bi, vlo, vhi);
     // children: bases, slot ranges, cursors (the full blocks are a prefix)
     const uint32_t c = t < IP_R ? S.tot[t] : 0u;
@@ -552,7 +626,9 @@ __global__ __launch_bounds__(IP_WG) void k_ip_medium(Plan p, Work w, IpWork iw, 
       const uint32_t L = S.fill[t];
       const uint32_t f = (base + B - 1) / B, lim = base + c, e = (lim + B - 1) / B;
       const uint32_t Fr = f < nbf ? min(e, nbf) - f : 0u;
-      M.W[t] = ((uint64_t)f << 32) | (uint64_t)(f + Fr + IP_BIAS);
+      // a bucket whose records all have one digit: its blocks are in place
+      const uint32_t wstart = c == count ? f + Fr : f;
+      M.W[t] = ((uint64_t)wstart << 32) | (uint64_t)(f + Fr + IP_BIAS);
       M.lim[t] = lim;
       M.base[t] = base;
       M.f[t] = f;
@@ -563,8 +639,7 @@ __global__ __launch_bounds__(IP_WG) void k_ip_medium(Plan p, Work w, IpWork iw, 
     __syncthreads();
     const Ranges rg{M.W, M.rinit, M.f, M.F, M.lim};
     uint32_t* recw = reinterpret_cast<uint32_t*>(rec + P * (uint64_t)(4 * RW));
-    for (uint32_t i = wave; i < IP_R; i += IP_WAVES)
-      ip_drain<RW>(rg, i, 0xFFFFFFFFu, recw, count, B, g, kf, M.done, 0, protw0, p.spin_limit, &iw.ctl->error);
+    ip_drain_multi<RW>(rg, wave, IP_WAVES, recw, count, B, g, kf, M.done, protw0, p.spin_limit, &iw.ctl->error);
     __syncthreads();
     // edges of each child: leftovers (LDS), then the part of its last block
     // past its end (aside area, written by other wavefronts of this group)
@@ -641,7 +716,7 @@ template <int RW>
 __global__ __launch_bounds__(IP_WG) void k_ip_ranges(Plan p, Work w, IpWork iw, uint32_t level, uint8_t* rec) {
   __shared__ uint32_t hpre[IP_MAX_STRIPES + 1], mpre[IP_MAX_STRIPES + 1];
   __shared__ uint32_t tmp16[IP_WAVES];
-  __shared__ uint32_t s_fr, s_h, s_m;
+  __shared__ uint32_t s_fr, s_h, s_pa, s_pb, s_na, s_nb, s_ca, s_cb;
   const uint32_t nr = iw.ctl->nranges;
   const uint32_t B = ip_block_records(RW), WB = B * RW;
   const Bucket* list = ip_list(p, w, level);
@@ -681,6 +756,7 @@ __global__ __launch_bounds__(IP_WG) void k_ip_ranges(Plan p, Work w, IpWork iw, 
     if (H != Mv && t == 0) atomicOr(&iw.ctl->error, 4u);
     const uint32_t moves = min(H, Mv);
     uint32_t* recw = reinterpret_cast<uint32_t*>(rec + Bk.begin * (uint64_t)(4 * RW));
+    uint8_t* bd = iw.bdig + Bk.begin / B;  // digit of each full block slot of the bucket
     for (uint32_t k = wave; k < moves; k += IP_WAVES) {
       const uint32_t jh = last_le(hpre, nsr, k), jm = last_le(mpre, nsr, k);
       const uint32_t sh = sa + jh, sm = sa + jm;
@@ -692,11 +768,86 @@ __global__ __launch_bounds__(IP_WG) void k_ip_ranges(Plan p, Work w, IpWork iw, 
       }
       const Blk x = blk_load(recw + (uint64_t)mslot * WB, WB, lane);
       blk_store(recw + (uint64_t)hslot * WB, x, WB, lane);
+      if (lane == 0) bd[hslot] = bd[mslot];
+    }
+    __syncthreads();
+    // Blocks already of this range's digit need not move: they are swapped
+    // to the range's front [f, f + O), and the cursors start past them
+    // (with skewed keys most of a heavy child's blocks are its own).  The
+    // prefix's foreign blocks and the rest's own blocks (as many of each)
+    // are collected in two LDS queues as the two parts are scanned, and
+    // swapped in pairs.
+    const uint32_t v = r - lb * IP_R;
+    auto digit_at = [&](uint32_t sl) -> uint32_t { return bd[sl]; };
+    uint32_t own = 0;
+    for (uint32_t s0 = f; s0 < cut; s0 += 4 * IP_WG) {
+      uint32_t d4[4];
+#pragma unroll
+      for (uint32_t h = 0; h < 4; h++) {
+        const uint32_t sl = s0 + h * IP_WG + t;
+        d4[h] = sl < cut ? digit_at(sl) : ~0u;
+      }
+#pragma unroll
+      for (uint32_t h = 0; h < 4; h++) own += d4[h] == v ? 1u : 0u;
+    }
+    own = wave_sum32(own);
+    if (t == 0) {
+      s_h = 0;
+      s_pa = f;
+      s_na = s_nb = 0;
+    }
+    __syncthreads();
+    if (lane == 0 && own) atomicAdd(&s_h, own);
+    __syncthreads();
+    const uint32_t O = s_h;
+    if (t == 0) s_pb = f + O;
+    uint32_t* qa = hpre;  // foreign blocks in [f, f + O)
+    uint32_t* qb = mpre;  // own blocks in [f + O, cut)
+    for (;;) {
+      __syncthreads();
+      const uint32_t pa = s_pa, pb = s_pb, na = s_na, nb = s_nb;
+      // all own or none: nothing to swap
+      if (O == 0 || O == Fr || (pa >= f + O && pb >= cut && na == 0 && nb == 0)) break;
+      if (t == 0) { s_ca = 0; s_cb = 0; }
+      __syncthreads();
+      const bool fa = na < IP_WG && pa < f + O, fb = nb < IP_WG && pb < cut;
+      if (fa && pa + t < f + O && digit_at(pa + t) != v) qa[na + atomicAdd(&s_ca, 1u)] = pa + t;
+      if (fb && pb + t < cut && digit_at(pb + t) == v) qb[nb + atomicAdd(&s_cb, 1u)] = pb + t;
+      __syncthreads();
+      const uint32_t na2 = na + s_ca, nb2 = nb + s_cb, k = min(na2, nb2);
+      for (uint32_t j = wave; j < k; j += IP_WAVES) {
+        const uint32_t sa_ = qa[j], sb_ = qb[j];
+        const Blk x = blk_load(recw + (uint64_t)sa_ * WB, WB, lane);
+        const Blk y = blk_load(recw + (uint64_t)sb_ * WB, WB, lane);
+        blk_store(recw + (uint64_t)sa_ * WB, y, WB, lane);
+        blk_store(recw + (uint64_t)sb_ * WB, x, WB, lane);
+      }
+      // drop the swapped pairs from the queues' fronts
+      uint32_t ka[2], kb[2];
+#pragma unroll
+      for (uint32_t h = 0; h < 2; h++) {
+        const uint32_t j = k + t + h * IP_WG;
+        ka[h] = j < na2 ? qa[j] : 0u;
+        kb[h] = j < nb2 ? qb[j] : 0u;
+      }
+      __syncthreads();
+#pragma unroll
+      for (uint32_t h = 0; h < 2; h++) {
+        const uint32_t j = k + t + h * IP_WG;
+        if (j < na2) qa[j - k] = ka[h];
+        if (j < nb2) qb[j - k] = kb[h];
+      }
+      if (t == 0) {
+        s_na = na2 - k;
+        s_nb = nb2 - k;
+        if (fa) s_pa = min(pa + IP_WG, f + O);
+        if (fb) s_pb = min(pb + IP_WG, cut);
+      }
     }
     if (t == 0) {
-      iw.W[(uint64_t)r * IP_WSTRIDE] = ((uint64_t)f << 32) | (uint64_t)(cut + IP_BIAS);
+      iw.W[(uint64_t)r * IP_WSTRIDE] = ((uint64_t)(f + O) << 32) | (uint64_t)(cut + IP_BIAS);
       iw.rinit[r] = cut;
-      iw.chunk_start[r] = (Fr + IP_CHUNK - 1) / IP_CHUNK;
+      iw.chunk_start[r] = (Fr - O + IP_CHUNK - 1) / IP_CHUNK;
     }
     __syncthreads();
   }
@@ -735,7 +886,7 @@ __global__ __launch_bounds__(IP_WG) void k_ip_chunks(IpWork iw) {
 }
 
 // Permutation of the large buckets' blocks.  A wavefront runs IP_CHAINS
-// chains at once, each carrying one block (the same steps as ip_drain): per
+// chains at once, each carrying one block (the steps of ip_drain_multi): per
 // round every chain issues its cursor claim -- a read claim on the wave's
 // current range if it holds no block, a write claim on its block's digit
 // otherwise -- then the block loads the claims call for, so that the

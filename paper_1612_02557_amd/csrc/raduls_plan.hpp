@@ -185,6 +185,7 @@ struct IpWork {
   uint32_t* rinit;         // cap_ranges: read cursor before the permutation
   uint32_t* chunk_start;   // cap_ranges + 1: permutation chunks of each range (prefix)
   uint32_t* done;          // done_words: one bit per block of the records, set once its reader has it
+  uint8_t* bdig;           // done_words x 32: digit of each full block of a large bucket (by block index)
   uint8_t* mscratch;       // grid_medium x IP_R x IP_BLOCK_BYTES: protruding records of the medium kernel
   uint64_t cap_large, cap_stripes, cap_ranges, done_words;
   uint32_t grid_medium;
