@@ -39,6 +39,10 @@ namespace {
 
 constexpr uint32_t IP_WAVES = IP_WG / 64;
 constexpr uint32_t IP_PERM_WG = 256;               // threads of the permutation workgroups
+// A range's blocks of its own digit are swapped to its front by its one
+// workgroup only if at most this many blocks of the range are foreign
+// (bounding the pairs it swaps); otherwise the permutation moves them all.
+constexpr uint32_t IP_OWN_SWAP_MAX = 1u << 16;
 
 __device__ __forceinline__ const Bucket* ip_list(const Plan& p, const Work& w, uint32_t level) {
   return w.big + (uint64_t)level * p.cap_big;
@@ -206,15 +210,16 @@ __device__ __forceinline__ void put_block(Blk x, uint32_t* recw, uint64_t count,
 
 // One wavefront moves blocks of the workgroup's own bucket (cursors and
 // bits in LDS) with four chains at a time.  A chain without a block takes
-// one from the back of a range (reads come from ranges first, first + step,
-// ... each until it is exhausted); a chain with a block of digit v claims
+// one from the back of a range (the wavefront visits every range once,
+// from `first` on, each until it is exhausted, so that all wavefronts help
+// drain a child that holds most blocks); a chain with a block of digit v claims
 // v's write slot: a slot still below v's read cursor holds an unread block,
 // which is taken out first and carried on; a slot claimed by a reader is
 // waited for through its bit (bounded).  Per round all chains' claims and
 // block loads are issued before any is waited for, and read bits are set
 // before any chain waits on one.
 template <int RW>
-__device__ void ip_drain_multi(const Ranges& rg, uint32_t first, uint32_t step, uint32_t* recw, uint64_t count,
+__device__ void ip_drain_multi(const Ranges& rg, uint32_t first, uint32_t* recw, uint64_t count,
                                uint32_t B, Dig g, const KeyFmt& kf, uint32_t* done, uint32_t* protw0,
                                uint32_t spin_limit, uint32_t* err) {
   constexpr uint32_t NC = 4;
@@ -222,8 +227,8 @@ __device__ void ip_drain_multi(const Ranges& rg, uint32_t first, uint32_t step, 
   const uint32_t WB = B * RW;
   const uint32_t PW = IP_BLOCK_BYTES / 4;
   const uint64_t nblk = (count + B - 1) / B;
-  uint32_t ri = first;
-  bool more = ri < IP_R;
+  uint32_t ri = first % IP_R, visited = 0;
+  bool more = true;
   Blk x[NC], y[NC];
   uint32_t v[NC], slot[NC], mode[NC];
   uint64_t lim[NC];
@@ -269,9 +274,9 @@ __device__ void ip_drain_multi(const Ranges& rg, uint32_t first, uint32_t step, 
         if (lane == 0) atomicOr(err, 4u);
         ngot = 0;
       }
-      if (ngot < nneed) {  // range exhausted: the next one
-        ri += step;
-        more = ri < IP_R;
+      if (ngot < nneed) {  // range exhausted (it stays so): the next one
+        ri = ri + 1 == IP_R ? 0u : ri + 1;
+        more = ++visited < IP_R;
       }
     }
     uint32_t k = 0;
@@ -639,7 +644,8 @@ __global__ __launch_bounds__(IP_WG) void k_ip_medium(Plan p, Work w, IpWork iw, 
     __syncthreads();
     const Ranges rg{M.W, M.rinit, M.f, M.F, M.lim};
     uint32_t* recw = reinterpret_cast<uint32_t*>(rec + P * (uint64_t)(4 * RW));
-    ip_drain_multi<RW>(rg, wave, IP_WAVES, recw, count, B, g, kf, M.done, protw0, p.spin_limit, &iw.ctl->error);
+    ip_drain_multi<RW>(rg, wave * (IP_R / IP_WAVES), recw, count, B, g, kf, M.done, protw0, p.spin_limit,
+                       &iw.ctl->error);
     __syncthreads();
     // edges of each child: leftovers (LDS), then the part of its last block
     // past its end (aside area, written by other wavefronts of this group)
@@ -799,15 +805,18 @@ __global__ __launch_bounds__(IP_WG) void k_ip_ranges(Plan p, Work w, IpWork iw, 
     __syncthreads();
     if (lane == 0 && own) atomicAdd(&s_h, own);
     __syncthreads();
-    const uint32_t O = s_h;
+    const uint32_t O0 = s_h;
+    const bool own_ok = O0 > 0 && O0 < Fr && Fr - O0 <= IP_OWN_SWAP_MAX;
+    const uint32_t O = (own_ok || O0 == Fr) ? O0 : 0u;  // blocks that stay in place
     if (t == 0) s_pb = f + O;
     uint32_t* qa = hpre;  // foreign blocks in [f, f + O)
     uint32_t* qb = mpre;  // own blocks in [f + O, cut)
     for (;;) {
       __syncthreads();
       const uint32_t pa = s_pa, pb = s_pb, na = s_na, nb = s_nb;
-      // all own or none: nothing to swap
-      if (O == 0 || O == Fr || (pa >= f + O && pb >= cut && na == 0 && nb == 0)) break;
+      // all own or none: nothing to swap; more than IP_OWN_SWAP_MAX foreign
+      // blocks (the pairs one workgroup would swap): left to the permutation
+      if (!own_ok || (pa >= f + O && pb >= cut && na == 0 && nb == 0)) break;
       if (t == 0) { s_ca = 0; s_cb = 0; }
       __syncthreads();
       const bool fa = na < IP_WG && pa < f + O, fb = nb < IP_WG && pb < cut;
