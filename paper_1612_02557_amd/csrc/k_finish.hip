@@ -332,8 +332,6 @@ __global__ __launch_bounds__(FWG) void k_fin_jobs(Plan p, Work w, uint8_t* rec0,
         asm volatile("" : "+v"(nv));
         km = phase_mask(kf.mlo);
         kmh = phase_mask(kf.mhi);
-      kmh = phase_mask(kf.mhi);
-    kmh = phase_mask(kf.mhi);
 #pragma unroll
         for (uint32_t u = 0; u < E; u++)
           if (u < nv) buf_store_rec<RW>(dr, q0 * RB, u * 64 * RB, r[u]);
@@ -355,7 +353,6 @@ __global__ __launch_bounds__(FWG) void k_fin_jobs(Plan p, Work w, uint8_t* rec0,
       asm volatile("" : "+v"(nv));
       km = phase_mask(kf.mlo);
       kmh = phase_mask(kf.mhi);
-    kmh = phase_mask(kf.mhi);
 #pragma unroll
       for (uint32_t u = 0; u < E; u++)
         if (u < nv) atomicAdd(&S.h8[low32(fkey_k<K, RW>(r[u], km, kmh) >> sh8) & 255u], 1u);
@@ -526,7 +523,6 @@ __global__ __launch_bounds__(FWG) void k_fin_jobs(Plan p, Work w, uint8_t* rec0,
       asm volatile("" : "+v"(nv));
       km = phase_mask(kf.mlo);
       kmh = phase_mask(kf.mhi);
-    kmh = phase_mask(kf.mhi);
 #pragma unroll
       for (uint32_t u = 0; u < E; u++) {
         uint32_t bi = FIN_SPLIT_MAX;
@@ -623,7 +619,6 @@ __global__ __launch_bounds__(FWG) void k_fin_jobs(Plan p, Work w, uint8_t* rec0,
       asm volatile("" : "+v"(nv));
       km = phase_mask(kf.mlo);
       kmh = phase_mask(kf.mhi);
-    kmh = phase_mask(kf.mhi);
 #pragma unroll
       for (uint32_t u = 0; u < E; u++) {
         const uint32_t o = ((slot2[u / 2] >> (16 * (u & 1))) & 0xFFFFu) - base;

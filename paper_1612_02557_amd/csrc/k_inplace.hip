@@ -210,8 +210,8 @@ __device__ __forceinline__ void put_block(Blk x, uint32_t* recw, uint64_t count,
 
 // One wavefront moves blocks of the workgroup's own bucket (cursors and
 // bits in LDS) with four chains at a time.  A chain without a block takes
-// one from the back of a range (the wavefront visits every range once,
-// from `first` on, each until it is exhausted, so that all wavefronts help
+// one from the back of a range (the wavefront visits every range once, its
+// own 16 first, each until it is exhausted, so that all wavefronts help
 // drain a child that holds most blocks); a chain with a block of digit v claims
 // v's write slot: a slot still below v's read cursor holds an unread block,
 // which is taken out first and carried on; a slot claimed by a reader is
@@ -227,7 +227,12 @@ __device__ void ip_drain_multi(const Ranges& rg, uint32_t first, uint32_t* recw,
   const uint32_t WB = B * RW;
   const uint32_t PW = IP_BLOCK_BYTES / 4;
   const uint64_t nblk = (count + B - 1) / B;
-  uint32_t ri = first % IP_R, visited = 0;
+  // visiting order: the wavefront's own ranges first, first + 16 b (b < 16),
+  // then those of the next wavefront, and so on: visit k = 16 a + b goes to
+  // range first + 16 b + a (mod 256), every range once
+  constexpr uint32_t NW = IP_R / 16;
+  auto range_of = [&](uint32_t k) -> uint32_t { return (first + 16u * (k % NW) + k / NW) % IP_R; };
+  uint32_t visited = 0, ri = range_of(0);
   bool more = true;
   Blk x[NC], y[NC];
   uint32_t v[NC], slot[NC], mode[NC];
@@ -248,6 +253,14 @@ __device__ void ip_drain_multi(const Ranges& rg, uint32_t first, uint32_t* recw,
     for (uint32_t c = 0; c < NC; c++) {
       nneed += has[c] ? 0u : 1u;
       busy = busy || has[c];
+    }
+    // ranges already drained are passed by a plain read of their word (a
+    // hint: the claim below decides)
+    while (nneed && more) {
+      const uint64_t wv = bcast64(__shfl((unsigned long long)rg.W[ri], 0));
+      if ((int64_t)(uint32_t)wv - (int64_t)IP_BIAS > (int64_t)(wv >> 32)) break;
+      more = ++visited < IP_R;
+      ri = range_of(visited);
     }
     if (!busy && !more) break;
     if (!more) nneed = 0;
@@ -275,8 +288,8 @@ __device__ void ip_drain_multi(const Ranges& rg, uint32_t first, uint32_t* recw,
         ngot = 0;
       }
       if (ngot < nneed) {  // range exhausted (it stays so): the next one
-        ri = ri + 1 == IP_R ? 0u : ri + 1;
         more = ++visited < IP_R;
+        ri = range_of(visited);
       }
     }
     uint32_t k = 0;
@@ -644,8 +657,7 @@ __global__ __launch_bounds__(IP_WG) void k_ip_medium(Plan p, Work w, IpWork iw, 
     __syncthreads();
     const Ranges rg{M.W, M.rinit, M.f, M.F, M.lim};
     uint32_t* recw = reinterpret_cast<uint32_t*>(rec + P * (uint64_t)(4 * RW));
-    ip_drain_multi<RW>(rg, wave * (IP_R / IP_WAVES), recw, count, B, g, kf, M.done, protw0, p.spin_limit,
-                       &iw.ctl->error);
+    ip_drain_multi<RW>(rg, wave, recw, count, B, g, kf, M.done, protw0, p.spin_limit, &iw.ctl->error);
     __syncthreads();
     // edges of each child: leftovers (LDS), then the part of its last block
     // past its end (aside area, written by other wavefronts of this group)
