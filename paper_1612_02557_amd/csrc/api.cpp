@@ -646,16 +646,16 @@ struct IpLayout {
   uint64_t cap_large, cap_stripes, cap_ranges, done_words;
 };
 
-// A large bucket holds more than SL = slb * B records, so there are at most
-// n / SL of them, and their stripes (ceil(count / SL) each) number at most
-// 2 n / SL + 2.
-IpLayout ip_layout_of(uint64_t n, uint32_t rw, uint64_t cap_big, uint32_t grid_medium, uint32_t slb) {
+// A large bucket holds more than mlb * B >= SL = slb * B records, so there
+// are at most n / (mlb * B) of them, and their stripes (ceil(count / SL)
+// each) number at most n / SL + n / (mlb * B) + 1 <= 2 n / SL + 2.
+IpLayout ip_layout_of(uint64_t n, uint32_t rw, uint64_t cap_big, uint32_t grid_medium, uint32_t slb, uint32_t mlb) {
   IpLayout L{};
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
   const uint64_t B = rd::ip_block_records(rw);
   const uint64_t SL = (uint64_t)slb * B;
-  L.cap_large = n / SL + 1;
+  L.cap_large = n / ((uint64_t)mlb * B) + 1;
   L.cap_stripes = 2 * (n / SL) + 2;
   L.cap_ranges = L.cap_large * rd::IP_R;
   L.done_words = (n / B + 2) / 32 + 2;
@@ -685,8 +685,9 @@ IpLayout ip_layout_of(uint64_t n, uint32_t rw, uint64_t cap_big, uint32_t grid_m
 
 int ensure_ip_workspace(DeviceState& s, const Plan& p) {
   const uint32_t slb = ip_slb();
+  const uint32_t mlb = slb == rd::IP_SLB ? rd::IP_MLB : slb;  // tests that shrink the stripe shrink both
   const uint32_t gm = (uint32_t)s.cu_count;
-  const IpLayout L = ip_layout_of(p.n, p.rw, p.cap_big, gm, slb);
+  const IpLayout L = ip_layout_of(p.n, p.rw, p.cap_big, gm, slb, mlb);
   if (L.total > s.ip_bytes) {
     if (s.ip_base) {
       HIPCHK(hipDeviceSynchronize());
@@ -730,6 +731,7 @@ int ensure_ip_workspace(DeviceState& s, const Plan& p) {
   w.done_words = L.done_words;
   w.grid_medium = gm;
   w.slb = slb;
+  w.mlb = mlb;
   return RADULS_OK;
 }
 
@@ -869,7 +871,7 @@ size_t raduls_inplace_workspace_bytes(uint64_t n, uint32_t rec_bytes, uint32_t k
   Plan p;
   if (make_inplace_plan(std::max<uint64_t>(n, 2), rec_bytes, key_bytes, 256, p)) return 0;
   const Layout L = layout_of(p);
-  return L.total + L.status_total + ip_layout_of(p.n, p.rw, p.cap_big, 256, rd::IP_SLB).total;
+  return L.total + L.status_total + ip_layout_of(p.n, p.rw, p.cap_big, 256, rd::IP_SLB, rd::IP_MLB).total;
 }
 
 int raduls_sort_noalloc(void* records, void* tmp, uint64_t n, uint32_t rec_bytes, uint32_t key_bytes, void* stream) {

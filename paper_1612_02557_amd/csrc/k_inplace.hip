@@ -27,8 +27,8 @@
 //    after its last full block -- receive its leftovers and the part of its
 //    last block that ran past its end (kept aside by that block's writer).
 //
-// A bucket of at most one stripe is done by one workgroup from start to end
-// (k_ip_medium), its buffers, cursors and bits in LDS.  The order of equal
+// A bucket of at most IP_MLB blocks is done by one workgroup from start to
+// end (k_ip_medium), its buffers, cursors and bits in LDS.  The order of equal
 // keys is not kept: the in-place sort is not stable.
 #include "raduls_dev.hpp"
 #include "raduls_kernels.hpp"
@@ -498,7 +498,8 @@ __global__ __launch_bounds__(IP_WG) void k_ip_setup(Plan p, Work w, IpWork iw, u
   const uint32_t t = threadIdx.x;
   const Bucket* list = ip_list(p, w, level);
   const uint32_t nb = (uint32_t)min((uint64_t)w.ctl->nbig[level], p.cap_big);
-  const uint64_t SL = (uint64_t)iw.slb * ip_block_records(p.rw);
+  const uint64_t SL = (uint64_t)iw.slb * ip_block_records(p.rw);  // records per stripe
+  const uint64_t ML = (uint64_t)iw.mlb * ip_block_records(p.rw);  // records of a one-workgroup bucket, at most
   if (t == 0) {
     run_l = run_s = run_m = 0;
     iw.ctl->stripe_ticket = 0;
@@ -510,7 +511,7 @@ __global__ __launch_bounds__(IP_WG) void k_ip_setup(Plan p, Work w, IpWork iw, u
   for (uint32_t c0 = 0; c0 < nb; c0 += IP_WG) {
     const uint32_t i = c0 + t;
     uint64_t cnt = i < nb ? list[i].count : 0;
-    const bool lg = i < nb && cnt > SL;
+    const bool lg = i < nb && cnt > ML;
     const uint64_t ns = lg ? (cnt + SL - 1) / SL : 0;
     if (ns > IP_MAX_STRIPES) bad = true;
     a[t] = lg ? 1u : 0u;
@@ -606,7 +607,7 @@ struct IpMed {
   uint64_t W[IP_R];
   uint64_t lim[IP_R];
   uint32_t base[IP_R], f[IP_R], F[IP_R], rinit[IP_R];
-  uint32_t done[IP_SLB / 32];
+  uint32_t done[IP_MLB / 32];
 };
 
 template <int RW>
@@ -653,7 +654,7 @@ __global__ __launch_bounds__(IP_WG) void k_ip_medium(Plan p, Work w, IpWork iw, 
       M.F[t] = (c - L) / B;
       M.rinit[t] = f + Fr;
     }
-    for (uint32_t i = t; i < IP_SLB / 32; i += IP_WG) M.done[i] = 0;
+    for (uint32_t i = t; i < (uint32_t)((count + 32ull * B - 1) / (32ull * B)); i += IP_WG) M.done[i] = 0;
     __syncthreads();
     const Ranges rg{M.W, M.rinit, M.f, M.F, M.lim};
     uint32_t* recw = reinterpret_cast<uint32_t*>(rec + P * (uint64_t)(4 * RW));
