@@ -556,17 +556,20 @@ def inplace_main(args):
         log(f"device check failed: {e}")
         verified = False
 
-    # algorithmic bytes: a level reads and writes its records twice (blocks
-    # by the classification, blocks moved by the permutation); finishing
-    # reads and writes once
+    # algorithmic bytes: a level reads and writes its records twice (into
+    # blocks, then the blocks into place): the records of the buckets split
+    # into stripes by the classification and the permutation (2r each), the
+    # others by the one-workgroup kernel (4r); finishing reads and writes once
     passes = []
-    for l, (n_in, _moved) in enumerate(work["levels"]):
-        for kind, kern in (("hist", "k_ip_classify"), ("scatter", "k_ip_permute")):
+    for l, (n_in, n_large) in enumerate(work["levels"]):
+        n_med = n_in - n_large
+        for kind, kern, recs, mult in (("hist", "k_ip_classify", n_large, 2), ("prep", "k_ip_medium", n_med, 4),
+                                       ("scatter", "k_ip_permute", n_large, 2)):
             name = f"L{l}.{kind}"
-            if name in phase_acc and n_in:
+            if name in phase_acc and recs:
                 t = statistics.mean(phase_acc[name])
-                b = 2 * r * n_in
-                passes.append({"phase": name, "kernel": kern, "ms": t, "records": n_in, "alg_bytes": b,
+                b = mult * r * recs
+                passes.append({"phase": name, "kernel": kern, "ms": t, "records": recs, "alg_bytes": b,
                                "GBps": b / t / 1e6 if t > 0 else None})
     if "small_jobs" in phase_acc:
         t = statistics.mean(phase_acc["small_jobs"])

@@ -296,7 +296,10 @@ int raduls_get_stats(raduls_stats* host_stats);
 int raduls_set_timing(int on);
 /* Device milliseconds of each launch group of the last raduls_sort run with
  * timing mode 2, waiting for it: index 0 setup; for level l (0..19) 1+4l
- * tile ranges and histogram reset, 2+4l histogram, 3+4l scan, 4+4l scatter;
+ * tile ranges and histogram reset, 2+4l histogram, 3+4l scan, 4+4l scatter
+ * (raduls_sort_inplace: 1+4l set-up and the one-workgroup buckets, 2+4l
+ * classification of the stripes, 3+4l children, ranges and cleanup, 4+4l
+ * block permutation);
  * 81 queue ordering, 82 single-workgroup queue pass, 83 single-workgroup
  * jobs pass, 84 copy-back.  `count` entries of host_ms are written (85 cover
  * every phase). */
@@ -304,7 +307,9 @@ int raduls_set_timing(int on);
 int raduls_phase_times(double* host_ms, uint32_t count);
 /* Records handled by each stage of the last sort, waiting for the device:
  * [2l] records in level l's buckets (histogram reads), [2l+1] records that
- * level moved (scatter), l = 0..19; [40] records queued for the
+ * level moved (scatter) -- for raduls_sort_inplace: the records of the
+ * buckets split into stripes among workgroups, the others being partitioned
+ * by one workgroup each -- l = 0..19; [40] records queued for the
  * single-workgroup kernel, [41] records in tiny buckets, [42] records copied
  * back from tmp, [43] records through one-workgroup radix passes (a record
  * counts once per pass), [44] records finished by wavefront jobs, [45]

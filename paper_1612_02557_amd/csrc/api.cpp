@@ -755,9 +755,10 @@ int make_inplace_plan(uint64_t n, uint32_t r, uint32_t k, int cus, Plan& p) {
   return RADULS_OK;
 }
 
-// Phase marks as for raduls_sort, read per level l as: 1+4l set-up,
-// 2+4l classification, 3+4l children, routing, ranges and cleanup, 4+4l
-// permutation; PH_SMALL tiny buckets, PH_JOBS finishing jobs.
+// Phase marks as for raduls_sort, read per level l as: 1+4l set-up and the
+// buckets of one workgroup (k_ip_medium), 2+4l classification of the
+// stripes, 3+4l children, routing, ranges and cleanup, 4+4l permutation;
+// PH_SMALL tiny buckets, PH_JOBS finishing jobs.
 void enqueue_inplace(DeviceState& s, const Plan& p, void* records, hipStream_t st, bool phases) {
   const Work& w = s.work;
   const rd::IpWork& iw = s.ipw;
@@ -774,6 +775,8 @@ void enqueue_inplace(DeviceState& s, const Plan& p, void* records, hipStream_t s
     pm.mark(1 + 4 * l);
     rd::launch_ip_classify(p, w, iw, l, records, cus, st);
     pm.mark(2 + 4 * l);
+    rd::launch_ip_medium(p, w, iw, l, records, st);
+    pm.mark(1 + 4 * l);
     rd::launch_ip_prepare(p, w, iw, l, records, cus, st);
     pm.mark(3 + 4 * l);
     rd::launch_ip_permute(p, w, iw, l, records, cus, st);
@@ -1118,7 +1121,12 @@ int raduls_last_work(uint64_t* host_out, uint32_t count) {
     v.resize(nb);
     if (nb) HIPCHK(hipMemcpy(v.data(), s.work.big + (uint64_t)l * p.cap_big, nb * sizeof(rd::Bucket), hipMemcpyDeviceToHost));
     uint64_t all = 0, moved = 0;
-    for (auto& b : v) { all += b.count; if (!(b.flags & rd::BF_SKIP)) moved += b.count; }
+    // in place: [2l+1] counts the records of the buckets split into stripes
+    const uint64_t ml = (uint64_t)s.ipw.mlb * rd::ip_block_records(p.rw);
+    for (auto& b : v) {
+      all += b.count;
+      if (p.inplace ? b.count > ml : !(b.flags & rd::BF_SKIP)) moved += b.count;
+    }
     put(2 * l, all);
     put(2 * l + 1, moved);
   }

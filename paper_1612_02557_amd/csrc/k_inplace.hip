@@ -1139,18 +1139,27 @@ __global__ __launch_bounds__(IP_WG) void k_ip_cleanup(Plan p, Work w, IpWork iw,
 
 // ---- launchers -------------------------------------------------------------------
 
-// set-up, classification of the stripes, buckets of one workgroup
+// set-up and classification of the stripes of the large buckets
 void launch_ip_classify(const Plan& p, const Work& w, const IpWork& iw, uint32_t level, void* records, int cus,
                         hipStream_t s) {
   uint8_t* rec = (uint8_t*)records;
   const size_t lds = (size_t)IP_R * IP_BLOCK_BYTES;
   k_ip_setup<<<1, IP_WG, 0, s>>>(p, w, iw, level);
   switch (p.rw) {
-#define RD_CASE(n)                                                          \
-  case n:                                                                   \
-    k_ip_classify<n><<<cus, IP_WG, lds, s>>>(p, w, iw, level, rec);         \
-    k_ip_medium<n><<<iw.grid_medium, IP_WG, lds, s>>>(p, w, iw, level, rec); \
-    break;
+#define RD_CASE(n) case n: k_ip_classify<n><<<cus, IP_WG, lds, s>>>(p, w, iw, level, rec); break;
+    RD_CASE(1) RD_CASE(2) RD_CASE(3) RD_CASE(4) RD_CASE(5) RD_CASE(6) RD_CASE(7) RD_CASE(8)
+    RD_CASE(9) RD_CASE(10) RD_CASE(11) RD_CASE(12) RD_CASE(13) RD_CASE(14) RD_CASE(15) RD_CASE(16)
+#undef RD_CASE
+    default: break;
+  }
+}
+
+// the buckets one workgroup partitions from start to end
+void launch_ip_medium(const Plan& p, const Work& w, const IpWork& iw, uint32_t level, void* records, hipStream_t s) {
+  uint8_t* rec = (uint8_t*)records;
+  const size_t lds = (size_t)IP_R * IP_BLOCK_BYTES;
+  switch (p.rw) {
+#define RD_CASE(n) case n: k_ip_medium<n><<<iw.grid_medium, IP_WG, lds, s>>>(p, w, iw, level, rec); break;
     RD_CASE(1) RD_CASE(2) RD_CASE(3) RD_CASE(4) RD_CASE(5) RD_CASE(6) RD_CASE(7) RD_CASE(8)
     RD_CASE(9) RD_CASE(10) RD_CASE(11) RD_CASE(12) RD_CASE(13) RD_CASE(14) RD_CASE(15) RD_CASE(16)
 #undef RD_CASE

@@ -24,9 +24,11 @@ void launch_small_jobs(const Plan& p, const Work& w, void* records, void* tmp, h
 void launch_fin_jobs(const Plan& p, const Work& w, void* records, void* tmp, hipStream_t s);
 void launch_copy(const Plan& p, const Work& w, void* records, const void* tmp, hipStream_t s);
 // one in-place level (k_inplace.hip), in this order: set-up and
-// classification; children, routing, ranges; permutation; cleanup
+// classification; the one-workgroup buckets; children, routing, ranges;
+// permutation; cleanup
 void launch_ip_classify(const Plan& p, const Work& w, const IpWork& iw, uint32_t level, void* records, int cus,
                         hipStream_t s);
+void launch_ip_medium(const Plan& p, const Work& w, const IpWork& iw, uint32_t level, void* records, hipStream_t s);
 void launch_ip_prepare(const Plan& p, const Work& w, const IpWork& iw, uint32_t level, void* records, int cus,
                        hipStream_t s);
 void launch_ip_permute(const Plan& p, const Work& w, const IpWork& iw, uint32_t level, void* records, int cus,
