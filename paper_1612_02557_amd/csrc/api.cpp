@@ -257,6 +257,13 @@ Plan make_plan(uint64_t n, uint32_t r, uint32_t k, const raduls_tuning& t, int c
   p.cap_tiny = std::min<uint64_t>(n + 1, child_bound) + 1;
   p.cap_copy = std::min<uint64_t>(n / 64 + 1, child_bound) + 1;
   p.cap_wg = p.cap_small + n / p.wave_cap + 2;
+  if (p.fin_max) {
+    // With register finishing no bucket reaches the single-workgroup queue:
+    // a child is a finishing job (a group of small children always is),
+    // tiny, done, or another level, and lmax levels resolve every key bit.
+    // The queue keeps a margin; an overflow would still be reported.
+    p.cap_small = std::min<uint64_t>(p.cap_small, 4096 + n / (p.fin_max * 8));
+  }
   p.max_tiles = n / p.tile + p.cap_big + 2;
   p.stack_cap = (uint32_t)std::min<uint64_t>(p.t_big / (p.c_fin + 1) + 4, 1u << 20);
   p.sched_mode = g_sched_mode;
