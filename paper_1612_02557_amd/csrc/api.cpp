@@ -636,15 +636,22 @@ int enqueue_runs(const void* sorted, uint64_t n, uint32_t r, uint32_t k, void* u
 
 // ---- in-place sorting --------------------------------------------------------
 
-// Blocks per stripe of the in-place levels; tests may lower it (through the
-// environment, read per call) so that small inputs take the multi-stripe path.
-uint32_t ip_slb() {
-  uint32_t v = rd::IP_SLB;
+// Blocks per stripe of the in-place levels: IP_SLB, longer when n would
+// give a bucket more than IP_MAX_STRIPES stripes; tests may lower it
+// (through the environment, read per call) so that small inputs take the
+// multi-stripe path.
+uint32_t ip_slb(uint64_t n, uint32_t rw, bool* test_set = nullptr) {
+  uint64_t v = rd::IP_SLB;
+  if (test_set) *test_set = false;
   if (const char* e = getenv("RADULS_TEST_IP_SLB")) {
     const unsigned long x = strtoul(e, nullptr, 10);
-    if (x >= 1 && x <= rd::IP_SLB) v = (uint32_t)x;
+    if (x >= 1 && x <= rd::IP_SLB) {
+      v = x;
+      if (test_set) *test_set = true;
+    }
   }
-  return v;
+  const uint64_t blocks = n / rd::ip_block_records(rw) + 1;
+  return (uint32_t)std::max<uint64_t>(v, blocks / rd::IP_MAX_STRIPES + 1);
 }
 
 struct IpLayout {
@@ -653,9 +660,9 @@ struct IpLayout {
   uint64_t cap_large, cap_stripes, cap_ranges, done_words;
 };
 
-// A large bucket holds more than mlb * B >= SL = slb * B records, so there
-// are at most n / (mlb * B) of them, and their stripes (ceil(count / SL)
-// each) number at most n / SL + n / (mlb * B) + 1 <= 2 n / SL + 2.
+// A large bucket holds more than ML = mlb * B records, so there are at most
+// n / ML of them, and their stripes (ceil(count / SL) each, SL = slb * B)
+// number at most n / SL + n / ML.
 IpLayout ip_layout_of(uint64_t n, uint32_t rw, uint64_t cap_big, uint32_t grid_medium, uint32_t slb, uint32_t mlb) {
   IpLayout L{};
   size_t o = 0;
@@ -663,7 +670,7 @@ IpLayout ip_layout_of(uint64_t n, uint32_t rw, uint64_t cap_big, uint32_t grid_m
   const uint64_t B = rd::ip_block_records(rw);
   const uint64_t SL = (uint64_t)slb * B;
   L.cap_large = n / ((uint64_t)mlb * B) + 1;
-  L.cap_stripes = 2 * (n / SL) + 2;
+  L.cap_stripes = n / SL + n / ((uint64_t)mlb * B) + 2;
   L.cap_ranges = L.cap_large * rd::IP_R;
   L.done_words = (n / B + 2) / 32 + 2;
   L.ctl = take(sizeof(rd::IpCtl));
@@ -691,8 +698,9 @@ IpLayout ip_layout_of(uint64_t n, uint32_t rw, uint64_t cap_big, uint32_t grid_m
 }
 
 int ensure_ip_workspace(DeviceState& s, const Plan& p) {
-  const uint32_t slb = ip_slb();
-  const uint32_t mlb = slb == rd::IP_SLB ? rd::IP_MLB : slb;  // tests that shrink the stripe shrink both
+  bool test_set = false;
+  const uint32_t slb = ip_slb(p.n, p.rw, &test_set);
+  const uint32_t mlb = test_set ? slb : rd::IP_MLB;  // tests that shrink the stripe shrink both
   const uint32_t gm = (uint32_t)s.cu_count;
   const IpLayout L = ip_layout_of(p.n, p.rw, p.cap_big, gm, slb, mlb);
   if (L.total > s.ip_bytes) {
@@ -881,7 +889,7 @@ size_t raduls_inplace_workspace_bytes(uint64_t n, uint32_t rec_bytes, uint32_t k
   Plan p;
   if (make_inplace_plan(std::max<uint64_t>(n, 2), rec_bytes, key_bytes, 256, p)) return 0;
   const Layout L = layout_of(p);
-  return L.total + L.status_total + ip_layout_of(p.n, p.rw, p.cap_big, 256, rd::IP_SLB, rd::IP_MLB).total;
+  return L.total + L.status_total + ip_layout_of(p.n, p.rw, p.cap_big, 256, ip_slb(p.n, p.rw), rd::IP_MLB).total;
 }
 
 int raduls_sort_noalloc(void* records, void* tmp, uint64_t n, uint32_t rec_bytes, uint32_t key_bytes, void* stream) {

@@ -364,7 +364,6 @@ struct IpCls {
   uint32_t blk[IP_R];   // the first of them (block index in the stripe)
   uint32_t tot[IP_R];   // records of each digit in the stripe
   uint32_t tmp4[IP_WAVES];
-  uint64_t tmp64[4];
   uint32_t wpos;        // blocks written at the stripe's front
   uint32_t item;
 };

@@ -149,7 +149,7 @@ struct Work {
 constexpr uint32_t IP_WG = 1024;          // threads of the in-place workgroups
 constexpr uint32_t IP_R = 256;            // digits of a level (8 bits)
 constexpr uint32_t IP_BLOCK_BYTES = 512;  // bytes of a block, at most
-constexpr uint32_t IP_SLB = 32768;        // blocks per stripe of a bucket split among workgroups
+constexpr uint32_t IP_SLB = 32768;        // blocks per stripe of a bucket split among workgroups (more for n above 2^28 blocks)
 constexpr uint32_t IP_MLB = 131072;       // blocks of a bucket done by one workgroup, at most (its read bits fill 16 KiB of LDS)
 constexpr uint32_t IP_MAX_STRIPES = 8192; // stripes of one bucket, at most
 constexpr uint32_t IP_CHUNK = 64;         // block reads per claim of the permutation
@@ -190,7 +190,7 @@ struct IpWork {
   uint8_t* mscratch;       // grid_medium x IP_R x IP_BLOCK_BYTES: protruding records of the medium kernel
   uint64_t cap_large, cap_stripes, cap_ranges, done_words;
   uint32_t grid_medium;
-  uint32_t slb;            // blocks per stripe (IP_SLB; smaller only in tests)
+  uint32_t slb;            // blocks per stripe (IP_SLB, longer for huge n, shorter only in tests)
   uint32_t mlb;            // blocks of a bucket one workgroup takes, at most (IP_MLB; the stripe in tests)
 };
 

@@ -109,6 +109,14 @@ def test_many_stripes(R, monkeypatch, slb, dist):
               f"inplace slb={slb} {dist} r={r} k={k} n={n}")
 
 
+def test_stripe_length_grows_with_n(R, monkeypatch):
+    """A bucket has at most 8192 stripes: with stripes of one block asked
+    for (test-only setting), 400,000 records of 16 bytes (12,500 blocks) get
+    stripes of two blocks instead, and sort exactly."""
+    monkeypatch.setenv("RADULS_TEST_IP_SLB", "1")
+    check(R, synth.generate(spec(400_000, seed=47)), 8, "inplace slb=1 n=400000 (stripe length grows)")
+
+
 def test_repeat_and_sizes_in_turn(R):
     """Calls of different sizes and shapes one after another (the workspace
     grows and is reused)."""
