@@ -150,7 +150,7 @@ constexpr uint32_t IP_WG = 1024;          // threads of the in-place workgroups
 constexpr uint32_t IP_R = 256;            // digits of a level (8 bits)
 constexpr uint32_t IP_BLOCK_BYTES = 512;  // bytes of a block, at most
 constexpr uint32_t IP_SLB = 32768;        // blocks per stripe of a bucket split among workgroups (more for n above 2^28 blocks)
-constexpr uint32_t IP_MLB = 131072;       // blocks of a bucket done by one workgroup, at most (its read bits fill 16 KiB of LDS)
+constexpr uint32_t IP_MLB = 147456;       // blocks of a bucket done by one workgroup, at most (its read bits fill 18 KiB of LDS)
 constexpr uint32_t IP_MAX_STRIPES = 8192; // stripes of one bucket, at most
 constexpr uint32_t IP_CHUNK = 64;         // block reads per claim of the permutation
 constexpr uint32_t IP_BIAS = 1u << 30;    // added to the read cursor so that extra decrements never borrow
